@@ -1,0 +1,221 @@
+/*
+ * pint.h — C interface of libpint, a parallel-in-time Newton ODE solver for
+ * AMD MI355X (gfx950).
+ *
+ * Method (Iacob, Razavi, Sarkka, arXiv 2511.01465, Sec. 3.2): the trajectory
+ * xi = (x_1..x_T) of the one-step scheme x_n = Phi(x_{n-1}) (classic RK4,
+ * eq. explicit-rk) is the root of h(xi) = [x_n - Phi(x_{n-1})]_{n=1..T}
+ * (eq. root-finding-problem).  Each Newton iteration (eqs. newton-step,
+ * newton-iterates) needs dx_n = J(x_{n-1}) dx_{n-1} - h_n, dx_1 = -h_1
+ * (eq. newton-step-recursion), an affine recursion evaluated as a prefix
+ * scan (eq. prefix-sum) under the composition of eq. assoc-operator:
+ *     (A2, b2) o (A1, b1) = (A2 A1, A2 b1 + b2)   (A1,b1 applied first).
+ *
+ * Conventions for every entry point
+ *   - All array arguments are DEVICE pointers unless stated otherwise, owned
+ *     by the caller.  The library never allocates or frees caller memory and
+ *     allocates no device memory on the solve path: scratch comes from the
+ *     caller's workspace `ws` (size from pint_workspace_bytes), 256-byte
+ *     aligned.
+ *   - Layouts are row-major and packed: a state is d contiguous scalars; a
+ *     trajectory of instance b is T_b consecutive states x_1..x_T (x_0 is
+ *     NOT stored; it is the x0 input); a batch of trajectories is packed one
+ *     instance after the other (CSR by `T_off`).  A matrix is d*d scalars,
+ *     row-major.  Scalars are double (PINT_F64) or float (PINT_F32) as
+ *     selected by `dtype`; residuals and tolerances are always double.
+ *   - Every call is asynchronous on `stream` (0 = the null stream) unless
+ *     its comment says otherwise; outputs are valid once the stream has
+ *     synchronised.  Calls on one workspace must not overlap.
+ *   - Errors are return codes; nothing aborts or throws.  Argument errors
+ *     are detected on the host before anything is launched.
+ */
+#ifndef PINT_H_
+#define PINT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* pint_stream_t; /* a hipStream_t */
+
+typedef enum {
+  PINT_OK = 0,
+  PINT_ERR_INVALID_ARG = 1, /* bad argument; nothing was launched          */
+  PINT_ERR_DEVICE = 2,      /* a HIP runtime call failed                   */
+  PINT_ERR_WORKSPACE = 3,   /* workspace missing or smaller than required  */
+  PINT_NOT_CONVERGED = 4,   /* per instance: max_iter reached; last iterate returned */
+  PINT_NONFINITE = 5,       /* per instance: a non-finite residual or state stopped Newton */
+  PINT_ERR_UNSUPPORTED = 6  /* system / dimension / dtype combination not built */
+} pint_status;
+
+typedef enum { PINT_F64 = 0, PINT_F32 = 1 } pint_dtype;
+
+/* Built-in vector fields f(x; theta).  Parameter vectors theta, in order:
+ *   LINEAR     f = M x                                  theta = M (d*d, row-major)
+ *   LOGISTIC   d=1: f = r x (1 - x/K)                   theta = (r, K)          [Sec. 4.1, eq. logistic]
+ *   VDP        d=2: (x, v)' = (v, mu (1-x^2) v - x)     theta = (mu)            [Sec. 4.1, eq. vdp]
+ *   CARTPOLE   d=4: (p, th, p', th')                    theta = (g, l, m_c, m_p)[Sec. 4.1, eq. cartpole, with th'^2]
+ *   LORENZ63   d=3                                      theta = (sigma, rho, beta)
+ *   LORENZ96   d>=4: f_i = (x_{i+1}-x_{i-2}) x_{i-1} - x_i + F   theta = (F)
+ *   KURAMOTO   f_i = w_i + K sum_j sin(x_j - x_i)       theta = (K, w_1..w_d)
+ */
+typedef enum {
+  PINT_SYS_LINEAR = 0,
+  PINT_SYS_LOGISTIC = 1,
+  PINT_SYS_VDP = 2,
+  PINT_SYS_CARTPOLE = 3,
+  PINT_SYS_LORENZ63 = 4,
+  PINT_SYS_LORENZ96 = 5,
+  PINT_SYS_KURAMOTO = 6
+} pint_system_id;
+
+typedef struct {
+  int32_t system;        /* pint_system_id                                      */
+  int32_t d;             /* state dimension                                     */
+  int32_t n_params;      /* must equal pint_n_params(system, d)                 */
+  int32_t params_shared; /* 1: one theta for every instance; 0: [B][n_params]   */
+  const void* params;    /* device pointer, solve dtype                         */
+} pint_system;
+
+typedef struct {
+  int32_t dtype;     /* pint_dtype                                               */
+  int32_t guess;     /* 0: initial iterate x_n = x0 for all n; 1: traj holds it  */
+  int64_t max_iter;  /* maximum Newton updates; <= 0 means T + 1                 */
+  int64_t window;    /* 0: the paper's plain Newton over all T steps;            */
+                     /* W >= 1: windowed safeguard (see pint_solve_varlen)       */
+  double tol;        /* stop when ||h(xi)||_inf < tol (strict)                   */
+  double guard;      /* windowed mode: an updated state with |x| > guard (or     */
+                     /* non-finite) ends the accepted part of the update         */
+  int32_t tile;      /* scan tile / chunk hint; 0 = library default              */
+  int32_t flags;     /* reserved, must be 0                                      */
+} pint_options;
+
+/* Number of parameters of `system` at dimension d, or -1 if not allowed. */
+int pint_n_params(int32_t system, int32_t d);
+
+/* Human-readable name of a status code (static storage). */
+const char* pint_status_string(int32_t status);
+
+/* 1 if the (system, d, dtype) combination is compiled into the library. */
+int pint_supported(int32_t system, int32_t d, int32_t dtype);
+
+/* Bytes of workspace needed by pint_solve / pint_solve_varlen for B
+ * instances with sum T = T_total and max T = T_max. */
+size_t pint_workspace_bytes(const pint_system* sys, int64_t B, int64_t T_total,
+                            int64_t T_max, const pint_options* opts);
+
+/*
+ * pint_solve_varlen — Newton's method on h(xi) = 0 for B independent
+ * instances with their own horizons (Sec. 3.2; the per-instance loop,
+ * residual test and window logic all run on the device, one persistent
+ * launch for the whole batch).
+ *
+ *   x0      [B][d]            initial states x_0
+ *   T_off   [B+1] int64       CSR offsets: instance b owns steps
+ *                             T_off[b]..T_off[b+1]-1 of traj; T_off[0] = 0
+ *   T_max   host int64        max_b (T_off[b+1]-T_off[b]) (sizes the launch)
+ *   traj    [T_off[B]][d]     in: the initial iterate if opts->guess = 1;
+ *                             out: the last iterate (x_1..x_T per instance)
+ *   iters   [B] int64         Newton updates applied (the paper's K is iters+1)
+ *   resid   [B] double        ||h||_inf of the returned iterate
+ *   status  [B] int32         PINT_OK / PINT_NOT_CONVERGED / PINT_NONFINITE
+ *
+ * Plain mode (window 0): iteration k evaluates h over all steps, stops if
+ * ||h||_inf < tol, otherwise applies the full Newton step.  This is the
+ * paper's method.  Windowed mode (window W >= 1, also when W >= T_b), a
+ * safeguard the paper does not state: with p the first step whose
+ * ||h_p||_inf >= tol, the Newton step is computed from dx_p = -h_p over
+ * steps p..min(T_b, p+W-1) only, steps
+ * before p are left as they are, and the update is accepted only below the
+ * first updated state that is non-finite or exceeds `guard`.  Both modes have
+ * the same fixed point (the sequential trajectory).
+ * Returns PINT_OK when launched; per-instance outcomes are in `status`.
+ */
+pint_status pint_solve_varlen(const pint_system* sys, int64_t B, const void* x0,
+                              double dt, const int64_t* T_off, int64_t T_max,
+                              const pint_options* opts, void* traj,
+                              int64_t* iters, double* resid, int32_t* status,
+                              void* ws, size_t ws_bytes, pint_stream_t stream);
+
+/* pint_solve — as pint_solve_varlen with every instance of length T
+ * (traj is [B][T][d]).  Single long instances of dense dimension use every
+ * compute unit; the host then waits on the stream once per batch of
+ * iterations to read the device-side convergence flag, so this call may
+ * block until the solve is done. */
+pint_status pint_solve(const pint_system* sys, int64_t B, const void* x0,
+                       double dt, int64_t T, const pint_options* opts,
+                       void* traj, int64_t* iters, double* resid,
+                       int32_t* status, void* ws, size_t ws_bytes,
+                       pint_stream_t stream);
+
+/* pint_seq_integrate — the sequential comparator x_n = Phi(x_{n-1}),
+ * n = 1..T_b, for every instance (eq. explicit-ode with classic RK4).
+ * T_off as in pint_solve_varlen; traj [T_off[B]][d] is written. */
+pint_status pint_seq_integrate(const pint_system* sys, int64_t B,
+                               const void* x0, double dt, const int64_t* T_off,
+                               int64_t T_max, int32_t dtype, void* traj,
+                               pint_stream_t stream);
+
+/* pint_residual — h_n = x_n - Phi(x_{n-1}) for every step of a uniform
+ * batch (eq. root-finding-problem): h [B][T][d], and hmax [B] (double) the
+ * infinity norm per instance (+inf if any entry is non-finite). */
+pint_status pint_residual(const pint_system* sys, int64_t B, const void* x0,
+                          double dt, int64_t T, int32_t dtype, const void* traj,
+                          void* h, double* hmax, pint_stream_t stream);
+
+/* pint_elements — the Newton-step elements of a uniform batch:
+ * A [B][T][d][d] with A_n = dPhi/dx at x_n (n = 0..T-1, x_0 = x0) and
+ * b [B][T][d] with b_n = -h_{n+1}, so that dx_{n+1} = A_n dx_n + b_n with
+ * dx_0 = 0 (eqs. newton-step-recursion, initialization). */
+pint_status pint_elements(const pint_system* sys, int64_t B, const void* x0,
+                          double dt, int64_t T, int32_t dtype,
+                          const void* traj, void* A, void* b,
+                          pint_stream_t stream);
+
+/* pint_affine_scan — the prefix scan of eq. prefix-sum for affine
+ * elements (eq. linear-model): for each of B independent sequences of N
+ * elements, z_{n+1} = A_n z_n + b_n from z_0 = z0 (z0 [B][d], or NULL for
+ * zero), written as z [B][N][d] (z[n] = z_{n+1}).  A [B][N][d][d],
+ * b [B][N][d].  Single-pass decoupled-lookback scan over tiles of `tile`
+ * elements (0 = default); workspace from pint_scan_workspace_bytes.
+ * Supported d: 1..8, 16, 32, 40, 64, 128. */
+size_t pint_scan_workspace_bytes(int32_t d, int64_t B, int64_t N, int32_t tile,
+                                 int32_t dtype);
+pint_status pint_affine_scan(int32_t d, int64_t B, int64_t N, int32_t dtype,
+                             const void* A, const void* b, const void* z0,
+                             void* z, int32_t tile, void* ws, size_t ws_bytes,
+                             pint_stream_t stream);
+
+/*
+ * pint_adjoint — gradient of a trajectory loss L(x_1..x_T) through the
+ * discrete solution map x_n = Phi(x_{n-1}; theta) of a uniform batch:
+ *   lambda_T = g_T, lambda_n = g_n + J(x_n)^T lambda_{n+1},
+ *   dL/dx0 = J(x_0)^T lambda_1, dL/dtheta = sum_n dPhi/dtheta(x_{n-1})^T lambda_n,
+ * i.e. the back substitution H^T lambda = g with the block-bidiagonal H of
+ * eq. (jacobian), computed as a reverse-time affine scan over the elements
+ * (J_n^T, g_n).
+ *   traj      [B][T][d]  the converged forward trajectory
+ *   g         [B][T][d]  dL/dx_n
+ *   dL_dx0    [B][d]
+ *   dL_dtheta [B][n_params] (per instance, also when params_shared = 1;
+ *             sum over instances for a shared theta), or NULL
+ *   seg       steps per recomputation segment: elements are recomputed from
+ *             traj segment by segment (memory seg*d*d per instance); 0 = T
+ *             (all elements at once).
+ */
+size_t pint_adjoint_workspace_bytes(const pint_system* sys, int64_t B, int64_t T,
+                                    int64_t seg, int32_t dtype);
+pint_status pint_adjoint(const pint_system* sys, int64_t B, const void* x0,
+                         double dt, int64_t T, int32_t dtype, const void* traj,
+                         const void* g, void* dL_dx0, void* dL_dtheta,
+                         int64_t seg, void* ws, size_t ws_bytes,
+                         pint_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PINT_H_ */

@@ -185,7 +185,8 @@ def newton(sys, params, dt, T, x0, guess=None, tol=1e-10, max_iter=None,
     """O2.  Returns dict(traj, status, iters, final_resid, hist).
 
     guess: None for the constant guess x_n = x0, or a [T, d] array.
-    window: 0 (or >= T) for the paper's plain method, else the window W.
+    window: 0 for the paper's plain method, else the window W (safeguarded
+    form, also when W >= T).
     """
     x0 = _f64(x0)
     d = x0.size

@@ -467,13 +467,14 @@ void orc_combine(int d, const double* Fl, const double* cl, const double* Fe,
 /*
  * traj holds the initial guess xi^(0) on entry and the last iterate on exit.
  *
- * Plain form (window <= 0 or window >= T), the paper's method: at iteration k
+ * Plain form (window <= 0), the paper's method: at iteration k
  * evaluate h(xi^(k)) over all T steps and r_k = ||h||_inf; stop if r_k < tol;
  * otherwise compute the Newton step by the forward substitution
  *   dx_1 = -h_1,  dx_n = (I + dg_{n-1}/dx_{n-1}) dx_{n-1} - h_n,
  * where I + dg/dx = dPhi/dx at x_{n-1}, and set xi <- xi + dxi.
  *
- * Windowed form (1 <= window < T), a safeguard the paper does not state:
+ * Windowed form (window >= 1, also when window >= T), a safeguard the paper
+ * does not state:
  * the steps before the first violation p = min{n : ||h_n||_inf >= tol} are
  * left untouched (their residuals no longer change), the forward
  * substitution runs only over [p, min(T, p + W - 1)] starting from
@@ -503,7 +504,7 @@ int orc_newton(int sys, int d, const double* P, double dt, int64_t T,
   double* dx = (double*)malloc(sizeof(double) * (size_t)T * sd);
   double* J = (double*)malloc(sizeof(double) * sd * sd);
   double* phi = (double*)malloc(sizeof(double) * sd);
-  int plain = (window <= 0 || window >= T);
+  int plain = (window <= 0);
 
   if (plain) {
     for (k = 0;; k++) {
@@ -540,8 +541,7 @@ int orc_newton(int sys, int d, const double* P, double dt, int64_t T,
       if (p > T) { status = ORC_OK; break; }
       if (!isfinite(hp_norm)) { status = ORC_NONFINITE; break; }
       if (k >= max_iter) { status = ORC_NOT_CONVERGED; break; }
-      int64_t end = p + window - 1;
-      if (end > T) end = T;
+      int64_t end = (window >= T - p + 1) ? T : p + window - 1;
       /* residuals over the rest of the window */
       double rwin = hp_norm;
       for (int64_t n = p + 1; n <= end; n++) {

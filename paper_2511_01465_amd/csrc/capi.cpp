@@ -1,0 +1,242 @@
+// The extern "C" entry points of libpint: argument checks on the host, then
+// dispatch to the small-d or dense-d kernels.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "../../include/pint.h"
+#include "internal.h"
+
+using namespace pint;
+
+namespace {
+
+int n_params_of(int32_t system, int32_t d) {
+  switch (system) {
+    case PINT_SYS_LINEAR: return d >= 1 ? d * d : -1;
+    case PINT_SYS_LOGISTIC: return d == 1 ? 2 : -1;
+    case PINT_SYS_VDP: return d == 2 ? 1 : -1;
+    case PINT_SYS_CARTPOLE: return d == 4 ? 4 : -1;
+    case PINT_SYS_LORENZ63: return d == 3 ? 3 : -1;
+    case PINT_SYS_LORENZ96: return d >= 4 ? 1 : -1;
+    case PINT_SYS_KURAMOTO: return d >= 1 ? d + 1 : -1;
+  }
+  return -1;
+}
+
+bool is_small(int32_t system, int32_t d) { return small_supported(system, d); }
+
+int check_sys(const pint_system* sys, int64_t B) {
+  if (!sys || B < 0) return PINT_ERR_INVALID_ARG;
+  if (n_params_of(sys->system, sys->d) < 0) return PINT_ERR_INVALID_ARG;
+  if (sys->n_params != n_params_of(sys->system, sys->d)) return PINT_ERR_INVALID_ARG;
+  if (B > 0 && !sys->params) return PINT_ERR_INVALID_ARG;
+  if (!small_supported(sys->system, sys->d) && !dense_supported(sys->system, sys->d))
+    return PINT_ERR_UNSUPPORTED;
+  return PINT_OK;
+}
+
+int check_opts(const pint_options* o) {
+  if (!o) return PINT_ERR_INVALID_ARG;
+  if (o->dtype != PINT_F64 && o->dtype != PINT_F32) return PINT_ERR_INVALID_ARG;
+  if (o->guess != 0 && o->guess != 1) return PINT_ERR_INVALID_ARG;
+  if (o->window < 0 || o->flags != 0 || o->tile < 0) return PINT_ERR_INVALID_ARG;
+  if (!(o->tol > 0.0) || std::isnan(o->guard) || !(o->guard > 0.0)) return PINT_ERR_INVALID_ARG;
+  return PINT_OK;
+}
+
+SolveArgs make_args(const pint_system* sys, int64_t B, const void* x0, double dt,
+                    const int64_t* T_off, int64_t T_uniform, int64_t T_max,
+                    const pint_options* o, void* traj, int64_t* iters, double* resid,
+                    int32_t* status, void* ws, size_t ws_bytes, pint_stream_t stream) {
+  SolveArgs a{};
+  a.system = sys->system;
+  a.d = sys->d;
+  a.dtype = o ? o->dtype : PINT_F64;
+  a.B = B;
+  a.x0 = x0;
+  a.params = sys->params;
+  a.pstride = sys->params_shared ? 0 : sys->n_params;
+  a.T_off = T_off;
+  a.T_uniform = T_uniform;
+  a.T_max = T_max;
+  a.traj = traj;
+  a.dt = dt;
+  if (o) {
+    a.tol = o->tol;
+    a.guard = o->guard;
+    a.window = o->window;
+    a.max_iter = o->max_iter > 0 ? o->max_iter : T_max + 1;
+    a.guess = o->guess;
+    a.tile = o->tile;
+  }
+  a.iters = iters;
+  a.resid = resid;
+  a.status = status;
+  a.ws = ws;
+  a.ws_bytes = ws_bytes;
+  a.stream = reinterpret_cast<hipStream_t>(stream);
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pint_n_params(int32_t system, int32_t d) { return n_params_of(system, d); }
+
+const char* pint_status_string(int32_t s) {
+  switch (s) {
+    case PINT_OK: return "ok";
+    case PINT_ERR_INVALID_ARG: return "invalid argument";
+    case PINT_ERR_DEVICE: return "device error";
+    case PINT_ERR_WORKSPACE: return "workspace missing or too small";
+    case PINT_NOT_CONVERGED: return "not converged within max_iter";
+    case PINT_NONFINITE: return "non-finite residual or state";
+    case PINT_ERR_UNSUPPORTED: return "unsupported system/dimension/dtype";
+  }
+  return "unknown status";
+}
+
+int pint_supported(int32_t system, int32_t d, int32_t dtype) {
+  if (dtype != PINT_F64 && dtype != PINT_F32) return 0;
+  if (n_params_of(system, d) < 0) return 0;
+  return (small_supported(system, d) || dense_supported(system, d)) ? 1 : 0;
+}
+
+size_t pint_workspace_bytes(const pint_system* sys, int64_t B, int64_t T_total, int64_t T_max,
+                            const pint_options* opts) {
+  if (!sys || !opts || B < 0) return 0;
+  if (is_small(sys->system, sys->d)) return small_ws_bytes(B);
+  pint_system s = *sys;
+  SolveArgs a = make_args(&s, B, nullptr, 0.0, nullptr, T_max, T_max, opts, nullptr, nullptr,
+                          nullptr, nullptr, nullptr, 0, nullptr);
+  (void)T_total;
+  return dense_ws_bytes(a);
+}
+
+static pint_status solve_common(const pint_system* sys, int64_t B, const void* x0, double dt,
+                                const int64_t* T_off, int64_t T_uniform, int64_t T_max,
+                                const pint_options* opts, void* traj, int64_t* iters,
+                                double* resid, int32_t* status, void* ws, size_t ws_bytes,
+                                pint_stream_t stream) {
+  if (int rc = check_sys(sys, B)) return (pint_status)rc;
+  if (int rc = check_opts(opts)) return (pint_status)rc;
+  if (!std::isfinite(dt) || T_max < 0 || T_uniform < 0) return PINT_ERR_INVALID_ARG;
+  if (B == 0) return PINT_OK;
+  if (!x0 || !iters || !resid || !status || (T_max > 0 && !traj)) return PINT_ERR_INVALID_ARG;
+  SolveArgs a = make_args(sys, B, x0, dt, T_off, T_uniform, T_max, opts, traj, iters, resid,
+                          status, ws, ws_bytes, stream);
+  int rc;
+  if (is_small(sys->system, sys->d)) {
+    rc = small_solve(a);
+  } else {
+    if (T_off) return PINT_ERR_UNSUPPORTED;  // dense dimensions: uniform batches only
+    rc = dense_solve(a);
+  }
+  return (pint_status)rc;
+}
+
+pint_status pint_solve_varlen(const pint_system* sys, int64_t B, const void* x0, double dt,
+                              const int64_t* T_off, int64_t T_max, const pint_options* opts,
+                              void* traj, int64_t* iters, double* resid, int32_t* status,
+                              void* ws, size_t ws_bytes, pint_stream_t stream) {
+  if (!T_off) return PINT_ERR_INVALID_ARG;
+  return solve_common(sys, B, x0, dt, T_off, 0, T_max, opts, traj, iters, resid, status, ws,
+                      ws_bytes, stream);
+}
+
+pint_status pint_solve(const pint_system* sys, int64_t B, const void* x0, double dt, int64_t T,
+                       const pint_options* opts, void* traj, int64_t* iters, double* resid,
+                       int32_t* status, void* ws, size_t ws_bytes, pint_stream_t stream) {
+  return solve_common(sys, B, x0, dt, nullptr, T, T, opts, traj, iters, resid, status, ws,
+                      ws_bytes, stream);
+}
+
+pint_status pint_seq_integrate(const pint_system* sys, int64_t B, const void* x0, double dt,
+                               const int64_t* T_off, int64_t T_max, int32_t dtype, void* traj,
+                               pint_stream_t stream) {
+  if (int rc = check_sys(sys, B)) return (pint_status)rc;
+  if ((dtype != PINT_F64 && dtype != PINT_F32) || T_max < 0 || !std::isfinite(dt))
+    return PINT_ERR_INVALID_ARG;
+  if (B == 0) return PINT_OK;
+  if (!x0 || !T_off || (T_max > 0 && !traj)) return PINT_ERR_INVALID_ARG;
+  pint_options o{};
+  o.dtype = dtype;
+  SolveArgs a = make_args(sys, B, x0, dt, T_off, 0, T_max, &o, traj, nullptr, nullptr, nullptr,
+                          nullptr, 0, stream);
+  int rc = is_small(sys->system, sys->d) ? small_seq(a) : dense_seq(a);
+  return (pint_status)rc;
+}
+
+pint_status pint_residual(const pint_system* sys, int64_t B, const void* x0, double dt, int64_t T,
+                          int32_t dtype, const void* traj, void* h, double* hmax,
+                          pint_stream_t stream) {
+  if (int rc = check_sys(sys, B)) return (pint_status)rc;
+  if ((dtype != PINT_F64 && dtype != PINT_F32) || T < 0 || !std::isfinite(dt))
+    return PINT_ERR_INVALID_ARG;
+  if (B == 0) return PINT_OK;
+  if (!x0 || !hmax || (T > 0 && !traj)) return PINT_ERR_INVALID_ARG;
+  pint_options o{};
+  o.dtype = dtype;
+  SolveArgs a = make_args(sys, B, x0, dt, nullptr, T, T, &o, const_cast<void*>(traj), nullptr,
+                          nullptr, nullptr, nullptr, 0, stream);
+  int rc = is_small(sys->system, sys->d) ? small_residual(a, h, hmax) : dense_residual(a, h, hmax);
+  return (pint_status)rc;
+}
+
+pint_status pint_elements(const pint_system* sys, int64_t B, const void* x0, double dt, int64_t T,
+                          int32_t dtype, const void* traj, void* A, void* b,
+                          pint_stream_t stream) {
+  if (int rc = check_sys(sys, B)) return (pint_status)rc;
+  if ((dtype != PINT_F64 && dtype != PINT_F32) || T < 0 || !std::isfinite(dt))
+    return PINT_ERR_INVALID_ARG;
+  if (B == 0 || T == 0) return PINT_OK;
+  if (!x0 || !traj || !A || !b) return PINT_ERR_INVALID_ARG;
+  pint_options o{};
+  o.dtype = dtype;
+  SolveArgs a = make_args(sys, B, x0, dt, nullptr, T, T, &o, const_cast<void*>(traj), nullptr,
+                          nullptr, nullptr, nullptr, 0, stream);
+  int rc = is_small(sys->system, sys->d) ? small_elements(a, A, b) : dense_elements(a, A, b);
+  return (pint_status)rc;
+}
+
+size_t pint_scan_workspace_bytes(int32_t d, int64_t B, int64_t N, int32_t tile, int32_t dtype) {
+  return scan_ws_bytes(d, B, N, tile, dtype);
+}
+
+pint_status pint_affine_scan(int32_t d, int64_t B, int64_t N, int32_t dtype, const void* A,
+                             const void* b, const void* z0, void* z, int32_t tile, void* ws,
+                             size_t ws_bytes, pint_stream_t stream) {
+  if (d < 1 || B < 0 || N < 0 || tile < 0 || (dtype != PINT_F64 && dtype != PINT_F32))
+    return PINT_ERR_INVALID_ARG;
+  if (B == 0 || N == 0) return PINT_OK;
+  if (!A || !b || !z) return PINT_ERR_INVALID_ARG;
+  return (pint_status)affine_scan(d, B, N, dtype, A, b, z0, z, tile, ws, ws_bytes,
+                                  reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t pint_adjoint_workspace_bytes(const pint_system* sys, int64_t B, int64_t T, int64_t seg,
+                                    int32_t dtype) {
+  if (!sys || B < 0 || T < 0 || seg < 0) return 0;
+  return adjoint_ws_bytes(sys->system, sys->d, B, T, seg, dtype);
+}
+
+pint_status pint_adjoint(const pint_system* sys, int64_t B, const void* x0, double dt, int64_t T,
+                         int32_t dtype, const void* traj, const void* g, void* dL_dx0,
+                         void* dL_dtheta, int64_t seg, void* ws, size_t ws_bytes,
+                         pint_stream_t stream) {
+  if (int rc = check_sys(sys, B)) return (pint_status)rc;
+  if ((dtype != PINT_F64 && dtype != PINT_F32) || T < 0 || seg < 0 || !std::isfinite(dt))
+    return PINT_ERR_INVALID_ARG;
+  if (sys->system == PINT_SYS_CARTPOLE && dL_dtheta) return PINT_ERR_UNSUPPORTED;
+  if (B == 0) return PINT_OK;
+  if (!x0 || !dL_dx0 || (T > 0 && (!traj || !g))) return PINT_ERR_INVALID_ARG;
+  pint_options o{};
+  o.dtype = dtype;
+  SolveArgs a = make_args(sys, B, x0, dt, nullptr, T, T, &o, const_cast<void*>(traj), nullptr,
+                          nullptr, nullptr, ws, ws_bytes, stream);
+  return (pint_status)adjoint(a, g, dL_dx0, dL_dtheta, seg);
+}
+
+}  // extern "C"

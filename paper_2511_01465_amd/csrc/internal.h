@@ -1,0 +1,64 @@
+// Host-side interface between the C entry points and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pint {
+
+// Everything a batched solve needs (device pointers unless noted).
+struct SolveArgs {
+  int32_t system, d, dtype;
+  int64_t B;
+  const void* x0;
+  const void* params;
+  int64_t pstride;        // scalars between instances' parameter vectors (0 = shared)
+  const int64_t* T_off;   // [B+1] or nullptr (uniform)
+  int64_t T_uniform;      // used when T_off == nullptr
+  int64_t T_max;          // host value
+  void* traj;
+  double dt, tol, guard;
+  int64_t window, max_iter;
+  int32_t guess;
+  int32_t tile;
+  int64_t* iters;
+  double* resid;
+  int32_t* status;
+  void* ws;
+  size_t ws_bytes;
+  hipStream_t stream;
+};
+
+// Status codes shared with the public header.
+enum { ST_OK = 0, ST_INVALID = 1, ST_DEVICE = 2, ST_WORKSPACE = 3, ST_NOT_CONVERGED = 4,
+       ST_NONFINITE = 5, ST_UNSUPPORTED = 6 };
+
+bool small_supported(int system, int d);
+bool dense_supported(int system, int d);
+
+size_t small_ws_bytes(int64_t B);
+int small_solve(const SolveArgs& a);
+int small_seq(const SolveArgs& a);
+int small_residual(const SolveArgs& a, void* h, double* hmax);
+int small_elements(const SolveArgs& a, void* A, void* b);
+
+size_t dense_ws_bytes(const SolveArgs& a);
+int dense_solve(const SolveArgs& a);
+int dense_seq(const SolveArgs& a);
+int dense_residual(const SolveArgs& a, void* h, double* hmax);
+int dense_elements(const SolveArgs& a, void* A, void* b);
+
+size_t scan_ws_bytes(int d, int64_t B, int64_t N, int tile, int dtype);
+int affine_scan(int d, int64_t B, int64_t N, int dtype, const void* A, const void* b,
+                const void* z0, void* z, int tile, void* ws, size_t ws_bytes, hipStream_t s);
+
+size_t adjoint_ws_bytes(int system, int d, int64_t B, int64_t T, int64_t seg, int dtype);
+int adjoint(const SolveArgs& a, const void* g, void* dL_dx0, void* dL_dth, int64_t seg);
+
+// Zero `n` 32-bit words with a kernel (no memset nodes in captured graphs).
+int fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+}  // namespace pint

@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every function include/pint.h declares
+(no GPU needed: nothing is computed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pint.h")
+LIB = os.path.join(ROOT, "paper_2511_01465_amd", "libpint.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pint_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ["pint_solve", "pint_solve_varlen", "pint_seq_integrate", "pint_adjoint",
+              "pint_affine_scan", "pint_workspace_bytes", "pint_status_string"]:
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpint.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpint.so not built")
+def test_host_side_queries_without_gpu():
+    import paper_2511_01465_amd as P
+    lib = P.load()
+    assert P.n_params(P.LORENZ96, 40) == 1 and P.n_params(P.KURAMOTO, 128) == 129
+    assert P.n_params(P.VDP, 3) == -1
+    assert P.status_string(P.NONFINITE).startswith("non-finite")
+    assert P.supported(P.LORENZ63, 3) and P.supported(P.VDP, 2, P.F32)
+    assert not P.supported(P.VDP, 3)
+    # argument errors are caught on the host before anything is launched
+    sysd = P.pint_system(P.LORENZ63, 3, 3, 1, None)
+    opts = P.make_options(P.F64, tol=-1.0)
+    rc = lib.pint_solve(ctypes.byref(sysd), 1, None, 1e-3, 16, ctypes.byref(opts),
+                        None, None, None, None, None, 0, None)
+    assert rc == P.ERR_INVALID_ARG
+    opts = P.make_options(P.F64)
+    bad = P.pint_system(P.LORENZ63, 3, 2, 1, None)   # wrong n_params
+    rc = lib.pint_solve(ctypes.byref(bad), 1, None, 1e-3, 16, ctypes.byref(opts),
+                        None, None, None, None, None, 0, None)
+    assert rc == P.ERR_INVALID_ARG
+    rc = lib.pint_solve(ctypes.byref(sysd), 0, None, 1e-3, 16, ctypes.byref(opts),
+                        None, None, None, None, None, 0, None)
+    assert rc == P.OK   # empty batch: nothing to do
