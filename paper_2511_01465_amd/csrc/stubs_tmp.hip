@@ -1,11 +1,5 @@
 #include "internal.h"
 namespace pint {
-bool dense_supported(int, int) { return false; }
-size_t dense_ws_bytes(const SolveArgs&) { return 0; }
-int dense_solve(const SolveArgs&) { return ST_UNSUPPORTED; }
-int dense_seq(const SolveArgs&) { return ST_UNSUPPORTED; }
-int dense_residual(const SolveArgs&, void*, double*) { return ST_UNSUPPORTED; }
-int dense_elements(const SolveArgs&, void*, void*) { return ST_UNSUPPORTED; }
 size_t scan_ws_bytes(int, int64_t, int64_t, int, int) { return 0; }
 int affine_scan(int, int64_t, int64_t, int, const void*, const void*, const void*, void*, int, void*, size_t, hipStream_t) { return ST_UNSUPPORTED; }
 size_t adjoint_ws_bytes(int, int, int64_t, int64_t, int64_t, int) { return 0; }

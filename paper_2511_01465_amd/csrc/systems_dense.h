@@ -1,0 +1,213 @@
+// Vector fields of dense state dimension, evaluated cooperatively by a wave
+// (lane l holds components l, l+64, ...), and the columns of the RK4
+// Jacobian computed from the stage points each system's way.
+#pragma once
+
+#include "device_common.h"
+
+namespace pint {
+
+// Stage points of one RK4 step kept in LDS for the Jacobian threads:
+// x[s] is the point where stage s+1 evaluates f (x[0] = x_{n-1}).
+template <typename T, int D>
+struct StageL96 {
+  T x[4][D];
+};
+
+template <typename T, int D>
+struct StageKur {
+  T c[4][D];  // cos of the stage points
+  T s[4][D];  // sin of the stage points
+  T C[4], S[4];
+};
+
+// ------------------------------------------------------------ Lorenz-96 --
+
+// f_i = (x_{i+1} - x_{i-2}) x_{i-1} - x_i + F, indices mod D (D <= 64).
+template <typename T, int DIM>
+struct DSysL96 {
+  static constexpr int D = DIM, NP = 1, R = 1;
+  static constexpr int NT = 256;           // threads per workgroup
+  static constexpr int QB = 2;             // threads per Jacobian column
+  static constexpr int RB = D / QB;        // rows per thread
+  static constexpr int JT = D * QB;        // threads per step for the Jacobian
+  static constexpr int SPP = NT >= JT ? NT / JT : 1;  // steps per Jacobian pass
+  using Stage = StageL96<T, D>;
+  static_assert(D >= 4 && D <= 64 && D % QB == 0 && RB >= 2, "Lorenz-96 dense path");
+
+  __device__ static void f(const T* P, const T (&x)[R], T (&out)[R], int lane) {
+    const int i = lane < D ? lane : 0;
+    const T xp1 = __shfl(x[0], (i + 1) % D, PINT_WAVE);
+    const T xm1 = __shfl(x[0], (i + D - 1) % D, PINT_WAVE);
+    const T xm2 = __shfl(x[0], (i + D - 2) % D, PINT_WAVE);
+    out[0] = (xp1 - xm2) * xm1 - x[0] + P[0];
+  }
+  // Save stage point s (R values of this lane) into the step's LDS record.
+  __device__ static void save_stage(Stage* st, int s, const T (&y)[R], int lane) {
+    if (lane < D) st->x[s][lane] = y[0];
+  }
+
+  // Thread `sub` (< JT) of a step: rows [q*RB, q*RB+RB) of column j = sub/QB
+  // of J = dPhi/dx; element (i, j) goes to out[i * rs + j * cs].  The QB
+  // threads of a column are adjacent lanes.  With u the current column of
+  // M_s and the cyclic stencil
+  //   (Jf u)_i = x_{i-1}(u_{i+1} - u_{i-2}) + (x_{i+1} - x_{i-2}) u_{i-1} - u_i,
+  // each thread needs u_{r0-2}, u_{r0-1} and u_{r0+RB} from its neighbours.
+  __device__ static void jac_thread(const Stage* st, const T*, int sub, T dt, T* out, int rs, int cs) {
+    const int j = sub / QB, q = sub % QB, r0 = q * RB;
+    const int lane = threadIdx.x % PINT_WAVE, base = lane - q;
+    const int nxt = base + (q + 1) % QB, prv = base + (q + QB - 1) % QB;
+    const T h2 = T(0.5) * dt, c6 = dt / T(6);
+    T u[RB], acc[RB];
+#pragma unroll
+    for (int i = 0; i < RB; i++) u[i] = (r0 + i == j) ? T(1) : T(0);
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      asm volatile("" ::: "memory");  // read this stage's LDS values here, not all up front
+      const T* x = st->x[s];
+      const T w = (s == 0 || s == 3) ? T(1) : T(2);
+      const T c = (s == 2) ? dt : h2;
+      // halo (old values): first row of the next part, last two of the previous
+      const T up_next = __shfl(u[0], nxt, PINT_WAVE);
+      T um1 = __shfl(u[RB - 1], prv, PINT_WAVE);
+      T um2 = __shfl(u[RB - 2], prv, PINT_WAVE);
+#pragma unroll
+      for (int k = 0; k < RB; k++) {
+        const int i = r0 + k;
+        const int ip1 = i + 1 == D ? 0 : i + 1;
+        const int im1 = i == 0 ? D - 1 : i - 1;
+        const int im2 = i >= 2 ? i - 2 : i + D - 2;
+        const T uk = u[k];
+        const T up1 = (k + 1 < RB) ? u[k + 1] : up_next;
+        const T K = x[im1] * (up1 - um2) + (x[ip1] - x[im2]) * um1 - uk;
+        acc[k] = (s == 0) ? K : acc[k] + w * K;
+        u[k] = ((i == j) ? T(1) : T(0)) + c * K;
+        um2 = um1;
+        um1 = uk;
+      }
+    }
+    T* o = out + j * cs;
+#pragma unroll
+    for (int k = 0; k < RB; k++) o[(r0 + k) * rs] = ((r0 + k == j) ? T(1) : T(0)) + c6 * acc[k];
+  }
+};
+
+// ------------------------------------------------------------- Kuramoto --
+
+// f_i = w_i + K sum_j sin(x_j - x_i) = w_i + K (cos x_i S - sin x_i C) with
+// S = sum_j sin x_j, C = sum_j cos x_j (the same sum, expanded).
+template <typename T, int DIM>
+struct DSysKur {
+  static constexpr int D = DIM, NP = DIM + 1, R = (DIM + 63) / 64;
+  static constexpr int NT = 256;
+  static constexpr int QB = 8;             // threads per Jacobian column
+  static constexpr int RB = D / QB;        // rows per thread
+  static constexpr int JT = D * QB;        // threads per step for the Jacobian
+  static constexpr int SPP = NT >= JT ? NT / JT : 1;
+  using Stage = StageKur<T, D>;
+  static_assert(D % 64 == 0 && D % QB == 0, "Kuramoto dense path: d a multiple of 64");
+
+  __device__ static void sums(const T (&x)[R], T (&sn)[R], T (&cs)[R], T& S, T& C, int lane) {
+    T ls = T(0), lc = T(0);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      sn[r] = sin(x[r]);
+      cs[r] = cos(x[r]);
+      ls += sn[r];
+      lc += cs[r];
+    }
+    S = wave_sum(ls);
+    C = wave_sum(lc);
+  }
+  __device__ static void f(const T* P, const T (&x)[R], T (&out)[R], int lane) {
+    T sn[R], cs[R], S, C;
+    sums(x, sn, cs, S, C, lane);
+#pragma unroll
+    for (int r = 0; r < R; r++) out[r] = P[1 + lane + 64 * r] + P[0] * (cs[r] * S - sn[r] * C);
+  }
+  __device__ static void save_stage(Stage* st, int s, const T (&y)[R], int lane) {
+    T sn[R], cs[R], S, C;
+    sums(y, sn, cs, S, C, lane);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      st->c[s][lane + 64 * r] = cs[r];
+      st->s[s][lane + 64 * r] = sn[r];
+    }
+    if (lane == 0) {
+      st->S[s] = S;
+      st->C[s] = C;
+    }
+  }
+
+  // Rows [q*RB, q*RB+RB) of column j = sub/QB of J = dPhi/dx.  With
+  // c = cos x, s = sin x:  (Jf u)_i = K (c_i (c.u) + s_i (s.u))
+  // - K (c_i C + s_i S) u_i, the dot products reduced over the QB adjacent
+  // lanes of the column.
+  __device__ static void jac_thread(const Stage* st, const T* P, int sub, T dt, T* out, int rs, int cs_) {
+    const int j = sub / QB, q = sub % QB, r0 = q * RB;
+    const T h2 = T(0.5) * dt, c6 = dt / T(6), Kc = P[0];
+    T u[RB], acc[RB];
+#pragma unroll
+    for (int i = 0; i < RB; i++) u[i] = (r0 + i == j) ? T(1) : T(0);
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      asm volatile("" ::: "memory");  // read this stage's LDS values here, not all up front
+      const T* cs = st->c[s] + r0;
+      const T* sn = st->s[s] + r0;
+      T a = T(0), b = T(0);
+#pragma unroll
+      for (int i = 0; i < RB; i++) {
+        a += cs[i] * u[i];
+        b += sn[i] * u[i];
+      }
+#pragma unroll
+      for (int off = 1; off < QB; off <<= 1) {
+        a += __shfl_xor(a, off, PINT_WAVE);
+        b += __shfl_xor(b, off, PINT_WAVE);
+      }
+      const T C = st->C[s], S = st->S[s];
+      const T w = (s == 0 || s == 3) ? T(1) : T(2);
+      const T c = (s == 2) ? dt : h2;
+#pragma unroll
+      for (int i = 0; i < RB; i++) {
+        const T ci = cs[i], si = sn[i];
+        const T K = Kc * (ci * a + si * b) - Kc * (ci * C + si * S) * u[i];
+        acc[i] = (s == 0) ? K : acc[i] + w * K;
+        u[i] = ((r0 + i == j) ? T(1) : T(0)) + c * K;
+      }
+    }
+    T* o = out + j * cs_;
+#pragma unroll
+    for (int i = 0; i < RB; i++) o[(r0 + i) * rs] = ((r0 + i == j) ? T(1) : T(0)) + c6 * acc[i];
+  }
+};
+
+// --------------------------------------------------------- wave RK4 step --
+
+// One RK4 step of a dense system by one wave.  x: this lane's components of
+// x_{n-1}; returns phi.  If st != nullptr the four stage points are saved.
+template <typename T, class S>
+__device__ __forceinline__ void wave_rk4(const T* P, T dt, const T (&x)[S::R], T (&phi)[S::R],
+                                         typename S::Stage* st, int lane) {
+  constexpr int R = S::R;
+  T k[R], acc[R], y[R];
+  const T h2 = T(0.5) * dt, c6 = dt / T(6);
+  if (st) S::save_stage(st, 0, x, lane);
+  S::f(P, x, k, lane);
+#pragma unroll
+  for (int r = 0; r < R; r++) { acc[r] = k[r]; y[r] = x[r] + h2 * k[r]; }
+  if (st) S::save_stage(st, 1, y, lane);
+  S::f(P, y, k, lane);
+#pragma unroll
+  for (int r = 0; r < R; r++) { acc[r] += T(2) * k[r]; y[r] = x[r] + h2 * k[r]; }
+  if (st) S::save_stage(st, 2, y, lane);
+  S::f(P, y, k, lane);
+#pragma unroll
+  for (int r = 0; r < R; r++) { acc[r] += T(2) * k[r]; y[r] = x[r] + dt * k[r]; }
+  if (st) S::save_stage(st, 3, y, lane);
+  S::f(P, y, k, lane);
+#pragma unroll
+  for (int r = 0; r < R; r++) phi[r] = x[r] + c6 * (acc[r] + k[r]);
+}
+
+}  // namespace pint
