@@ -1,0 +1,207 @@
+"""Benchmark: converged steps x instances per second of the parallel-in-time
+Newton solver on one MI355X.
+
+Workload (default): Lorenz-96, d = 40, F = 8, RK4 dt = 0.005, T = 65536 steps,
+one instance, x0 = F + N(0, 0.01^2) (seed 2), FP64, stop when the max-abs
+residual < 1e-10, windowed Newton (window 32).  One "step" of the benchmark
+is one whole solve: from the constant initial iterate to convergence, inputs
+resident in HBM.  The sequential RK4 integrator on the GPU is timed beside it
+(the comparator), and the same solve in FP32.  The CPU oracle is timed on a
+bounded prefix of the same workload.
+
+Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits: this
+build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_HBM = 8.0e12
+
+
+def lorenz96_step_flops(d: int, window: int) -> dict:
+    """Algorithmic flops of one Newton update over a window of Lorenz-96 d.
+
+    Per window step: the RK4 step (4 f evaluations of ~6 flops per component
+    plus stage updates, ~50 d), the Jacobian by the chain rule through the
+    stages with the 4-nonzero stencil (4 stages x 8 d^2 for Jf M, 3 x 2 d^2
+    for the M updates, 4 x 2 d^2 for the accumulation: 46 d^2), the
+    recursion (2 d^2).  The residual search costs about one RK4 step per
+    searched step."""
+    per_step = 50 * d + 46 * d * d + 2 * d * d
+    return dict(per_window_step=per_step, per_update=window * per_step + 10 * 50 * d)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--T", type=int, default=65536)
+    ap.add_argument("--window", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=3072, help="oracle prefix length (steps)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and comparator legs")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2511_01465_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    w = W.lorenz96(T=args.T, window=args.window)
+    T, d, B = args.T, w.d, w.B
+    x0 = torch.tensor(w.x0, device=dev)
+    prm = torch.tensor(w.params, device=dev)
+    sysd = P.make_system(P.LORENZ96, d, prm, False)
+    opts = P.make_options(P.F64, tol=w.tol, window=args.window, max_iter=0)
+    traj = torch.empty((B, T, d), dtype=torch.float64, device=dev)
+    iters = torch.empty(B, dtype=torch.int64, device=dev)
+    resid = torch.empty(B, dtype=torch.float64, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    ws = torch.empty(P.pint_workspace_bytes(sysd, B, B * T, T, opts), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def solve_once():
+        rc = P.pint_solve(sysd, B, x0, w.dt, T, opts, traj, iters, resid, status, ws, stream)
+        if rc != 0:
+            raise RuntimeError(P.status_string(rc))
+
+    print(f"[bench] lorenz96 d={d} T={T} B={B} window={args.window} fp64: warmup {args.warmup}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        solve_once()
+    torch.cuda.synchronize()
+
+    # timed region: K whole solves, events on the launch stream around each
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t_all0 = torch.cuda.Event(enable_timing=True)
+    t_all1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_all0.record(stream)
+    for k in range(args.steps):
+        starts[k].record(stream)
+        solve_once()
+        ends[k].record(stream)
+    t_all1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_all0.elapsed_time(t_all1)
+    ms_per_step = ms_total / args.steps
+    launch_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    st = int(status[0])
+    n_iter = int(iters[0])
+    r_final = float(resid[0])
+    print(f"[bench] fp64 solve: {ms_per_step:.3f} ms/solve, status={st}, updates={n_iter}, "
+          f"resid={r_final:.3e}", file=sys.stderr, flush=True)
+    value = B * T / (ms_per_step / 1e3)
+
+    # FP64 defect of the returned trajectory, by the oracle's RK4 (checking only)
+    defect = None
+    try:
+        import oracle
+        h = oracle.residual(w.system, w.params[0], w.dt, w.x0[0], traj[0].cpu().numpy())
+        defect = float(np.abs(h).max())
+    except Exception as e:  # pragma: no cover
+        print(f"[bench] defect check skipped: {e}", file=sys.stderr)
+
+    extra = {}
+    if not args.no_extra:
+        # sequential RK4 on the GPU (the comparator), same inputs
+        T_off = torch.tensor([0, T], dtype=torch.int64, device=dev)
+        seq = torch.empty((T, d), dtype=torch.float64, device=dev)
+        for _ in range(2):
+            P.pint_seq_integrate(sysd, B, x0, w.dt, T_off, T, P.F64, seq, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(3, args.steps)
+        e0.record(stream)
+        for _ in range(reps):
+            P.pint_seq_integrate(sysd, B, x0, w.dt, T_off, T, P.F64, seq, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        seq_ms = e0.elapsed_time(e1) / reps
+        extra["sequential_gpu"] = {"value": B * T / (seq_ms / 1e3), "ms_per_solve": seq_ms,
+                                   "speedup_of_newton": value / (B * T / (seq_ms / 1e3))}
+        # FP32 solve (tol at FP32 resolution), error against the FP64 oracle
+        x32, p32 = x0.float(), prm.float()
+        tr32, it32, rs32, st32 = P.solve(P.LORENZ96, x32, p32, w.dt, T, tol=2e-5,
+                                         window=args.window)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(max(1, args.steps // 2)):
+            tr32, it32, rs32, st32 = P.solve(P.LORENZ96, x32, p32, w.dt, T, tol=2e-5,
+                                             window=args.window)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms32 = e0.elapsed_time(e1) / max(1, args.steps // 2)
+        fp32 = {"value": B * T / (ms32 / 1e3), "ms_per_solve": ms32, "status": int(st32[0]),
+                "updates": int(it32[0]), "tol": 2e-5}
+        try:
+            import oracle
+            got = tr32[0].double().cpu().numpy()
+            ref = oracle.integrate(w.system, w.params[0].astype(np.float32).astype(np.float64),
+                                   w.dt, 200, w.x0[0].astype(np.float32).astype(np.float64))
+            fp32["max_rel_err_vs_fp64_first200"] = float(np.abs(got[:200] - ref).max() / np.abs(ref).max())
+        except Exception:
+            pass
+        extra["fp32"] = fp32
+
+    flops = lorenz96_step_flops(d, args.window)
+    alg_flops = n_iter * flops["per_update"]
+    achieved = alg_flops / (launch_ms / 1e3)
+    roofline = {"kernel": "k_newton_dense<double, lorenz96 d=40>", "bound": "alu",
+                "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                "algorithmic_flops_per_launch": alg_flops, "launch_ms": launch_ms}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        Ts = min(args.cpu_sample, T)
+        print(f"[bench] cpu oracle on the first {Ts} steps", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        r = oracle.newton(w.system, w.params[0], w.dt, Ts, w.x0[0], tol=w.tol, window=args.window,
+                          max_iter=4 * Ts)
+        dt_cpu = time.perf_counter() - t0
+        cpu = {"value": Ts / dt_cpu, "unit": "converged steps*instances/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"oracle windowed Newton (W={args.window}, tol 1e-10) on the first {Ts} "
+                         f"of the {T} steps, one instance, one thread: {dt_cpu:.1f} s, "
+                         f"{r['iters']} updates, status {r['status']}"}
+
+    out = {
+        "metric": "converged steps*instances/sec (scan vs sequential, 1e-10 err); adjoint grads/sec",
+        "value": value, "unit": "converged steps*instances/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"lorenz96 d={d} F=8 dt=0.005 T={T} B={B} seed=2, windowed "
+                               f"Newton W={args.window}, tol 1e-10",
+                   "parallelism": "single GPU"},
+        "solve": {"status": st, "updates": n_iter, "final_resid": r_final, "fp64_defect": defect},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
