@@ -1,0 +1,517 @@
+// Single-pass prefix scan of affine elements (eq. prefix-sum over the
+// operator of eq. assoc-operator): z_{n+1} = A_n z_n + b_n for B independent
+// sequences, with decoupled lookback across tiles.
+//
+// Every tile takes its id from an atomic counter at start (so a tile only
+// ever waits on tiles that are already running), reduces its elements to an
+// aggregate map, publishes it, then walks back over its predecessors'
+// descriptors until it finds one whose inclusive prefix is known.  Because
+// the prefix starts from a known z_0, an inclusive prefix is just the vector
+// z at the tile's end, and stepping back over an aggregate-only predecessor
+// costs a matrix-vector product, not a matrix product.  Descriptors are
+// published payload first, then a device-scope fence, then the flag; waits
+// are bounded so every wave exits even if a predecessor never publishes.
+//
+//   small d (<= 8): tiles staged through LDS, each thread folds a run of
+//     elements, wave shuffles + LDS scan the thread aggregates;
+//   dense d (16..128): each tile folds its elements with MFMA matrix
+//     products (FP64 16x16x4 or FP32 16x16x4), the running product in LDS.
+#include "internal.h"
+#include "device_common.h"
+
+namespace pint {
+
+struct ScanArgs {
+  int64_t B, N, tiles_per_seq;
+  int32_t L;               // elements per tile
+  const void* A;
+  const void* b;
+  const void* z0;
+  void* z;
+  uint32_t* counter;
+  uint32_t* err;
+  uint32_t* flags;         // [B * tiles_per_seq]
+  void* agg;               // [B * tiles_per_seq][D*D + D]
+  void* incl;              // [B * tiles_per_seq][D]
+};
+
+constexpr uint32_t FLAG_AGG = 1, FLAG_INCL = 2;
+constexpr uint64_t SPIN_LIMIT = 1ull << 24;
+
+__device__ __forceinline__ void publish_flag(uint32_t* f, uint32_t v) {
+  __threadfence();
+  __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until the flag is non-zero (bounded); returns it (0 on timeout, after
+// raising the error word).  The fence after a non-zero flag orders the
+// payload reads after it.
+__device__ __forceinline__ uint32_t wait_flag(const uint32_t* f, uint32_t* err) {
+  for (uint64_t it = 0;; it++) {
+    const uint32_t v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v) {
+      __threadfence();
+      return v;
+    }
+    if (it > SPIN_LIMIT) {
+      atomicOr(err, 1u);
+      return 0;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_payload(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ----------------------------------------------------------- small d ------
+
+template <int D, typename T>
+constexpr int small_nt() { return D <= 4 ? 256 : 64; }
+
+template <int D, typename T>
+constexpr int small_s() {
+  constexpr int bytes = (D * D + D) * (int)sizeof(T) * small_nt<D, T>();
+  constexpr int s = 49152 / bytes;
+  return s < 1 ? 1 : (s > 16 ? 16 : s);
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
+  constexpr int NT = small_nt<D, T>(), S = small_s<D, T>(), TILE = NT * S, NW = NT / PINT_WAVE;
+  constexpr int E = D * D + D;
+  __shared__ T s_el[TILE * E];
+  __shared__ Aff<T, D> s_aff[NW];
+  __shared__ Aff<T, D> s_tagg;
+  __shared__ T s_zin[D], s_wz[NW][D];
+  __shared__ uint32_t s_tile;
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  if (tid == 0) s_tile = atomicAdd(a.counter, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t seq = tile / a.tiles_per_seq, ts = tile % a.tiles_per_seq;
+  const int64_t e0 = ts * TILE;
+  const int n_el = (int)((a.N - e0) < TILE ? (a.N - e0) : TILE);
+  const T* Ag = static_cast<const T*>(a.A) + (seq * a.N + e0) * D * D;
+  const T* bg = static_cast<const T*>(a.b) + (seq * a.N + e0) * D;
+  T* sA = s_el;
+  T* sb = s_el + TILE * D * D;
+  for (int i = tid; i < n_el * D * D; i += NT) sA[i] = Ag[i];
+  for (int i = tid; i < n_el * D; i += NT) sb[i] = bg[i];
+  __syncthreads();
+
+  // each thread folds its S consecutive elements into one map
+  Aff<T, D> agg;
+  aff_identity(agg);
+#pragma unroll
+  for (int s = 0; s < S; s++) {
+    const int idx = tid * S + s;
+    if (idx < n_el) {
+      Aff<T, D> e;
+#pragma unroll
+      for (int i = 0; i < D * D; i++) e.A[i] = sA[idx * D * D + i];
+#pragma unroll
+      for (int i = 0; i < D; i++) e.b[i] = sb[idx * D + i];
+      aff_after(e, agg);
+      agg = e;
+    }
+  }
+  block_scan_aff<T, D, NT>(agg, s_aff);  // agg: threads 0..tid composed
+  if (tid == NT - 1) s_tagg = agg;
+  __syncthreads();
+
+  // lookback: z at the start of this tile
+  if (tid == 0) {
+    const int64_t base = seq * a.tiles_per_seq;
+    uint32_t* flags = a.flags + base;
+    T* aggp = static_cast<T*>(a.agg) + base * E;
+    T* inclp = static_cast<T*>(a.incl) + base * D;
+    T z[D];
+    if (ts == 0) {
+#pragma unroll
+      for (int i = 0; i < D; i++) z[i] = a.z0 ? static_cast<const T*>(a.z0)[seq * D + i] : T(0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < D * D; i++) aggp[ts * E + i] = s_tagg.A[i];
+#pragma unroll
+      for (int i = 0; i < D; i++) aggp[ts * E + D * D + i] = s_tagg.b[i];
+      publish_flag(flags + ts, FLAG_AGG);
+      int64_t j = ts - 1;
+      for (;;) {
+        const uint32_t f = wait_flag(flags + j, a.err);
+        if (f == FLAG_INCL || f == 0) break;
+        j--;
+      }
+#pragma unroll
+      for (int i = 0; i < D; i++) z[i] = ld_payload(inclp + j * D + i);
+      for (int64_t m = j + 1; m < ts; m++) {
+        T t[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          T acc = ld_payload(aggp + m * E + D * D + i);
+#pragma unroll
+          for (int k = 0; k < D; k++) acc += ld_payload(aggp + m * E + i * D + k) * z[k];
+          t[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < D; i++) z[i] = t[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) s_zin[i] = z[i];
+    // this tile's inclusive prefix: its aggregate applied to z_in
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      T acc = s_tagg.b[i];
+#pragma unroll
+      for (int k = 0; k < D; k++) acc += s_tagg.A[i * D + k] * z[k];
+      inclp[ts * D + i] = acc;
+    }
+    publish_flag(flags + ts, FLAG_INCL);
+  }
+  __syncthreads();
+
+  // z at the end of each thread's run, then at its start (previous thread)
+  T zin[D], zend[D], z[D];
+#pragma unroll
+  for (int i = 0; i < D; i++) zin[i] = s_zin[i];
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    T acc = agg.b[i];
+#pragma unroll
+    for (int k = 0; k < D; k++) acc += agg.A[i * D + k] * zin[k];
+    zend[i] = acc;
+  }
+  if (lane == PINT_WAVE - 1)
+#pragma unroll
+    for (int i = 0; i < D; i++) s_wz[wv][i] = zend[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const T up = __shfl_up(zend[i], 1, PINT_WAVE);
+    z[i] = lane > 0 ? up : (wv > 0 ? s_wz[wv - 1][i] : zin[i]);
+  }
+  T out[S][D];
+#pragma unroll
+  for (int s = 0; s < S; s++) {
+    const int idx = tid * S + s;
+    if (idx < n_el) {
+      T t[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        T acc = sb[idx * D + i];
+#pragma unroll
+        for (int k = 0; k < D; k++) acc += sA[idx * D * D + i * D + k] * z[k];
+        t[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        z[i] = t[i];
+        out[s][i] = t[i];
+      }
+    }
+  }
+  __syncthreads();  // staging area is rewritten below
+#pragma unroll
+  for (int s = 0; s < S; s++) {
+    const int idx = tid * S + s;
+    if (idx < n_el)
+#pragma unroll
+      for (int i = 0; i < D; i++) sA[idx * D + i] = out[s][i];
+  }
+  __syncthreads();
+  T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
+  for (int i = tid; i < n_el * D; i += NT) zg[i] = sA[i];
+}
+
+// ----------------------------------------------------------- dense d ------
+
+typedef double pint_d4 __attribute__((ext_vector_type(4)));
+typedef float pint_f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {  // v_mfma_f64_16x16x4f64: acc (lane l, reg r) = (l/16 + 4r, l%16)
+  using acc_t = pint_d4;
+  __device__ static acc_t mma(double x, double y, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int r) { return lane / 16 + 4 * r; }
+};
+template <>
+struct Mfma<float> {  // v_mfma_f32_16x16x4f32: acc (lane l, reg r) = (4(l/16) + r, l%16)
+  using acc_t = pint_f4;
+  __device__ static acc_t mma(float x, float y, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+
+template <int D>
+struct DenseScanShape {
+  static constexpr int DP = (D + 15) / 16 * 16;    // padded to MFMA tiles
+  static constexpr int NTL = DP / 16;               // 16x16 tiles per dimension
+  static constexpr int PS = (DP % 32 == 0) ? DP + 16 : DP;  // LDS row stride
+  static constexpr int NT = 256, NW = 4;
+  static constexpr int RT = (NTL + NW - 1) / NW;   // row tiles per wave
+};
+
+template <typename T, int D>
+constexpr size_t dense_scan_lds() {
+  using SH = DenseScanShape<D>;
+  return (size_t)SH::DP * SH::PS * sizeof(T) + 4 * (size_t)SH::DP * sizeof(T);
+}
+
+// z <- M z + c for a D x D row-major M in global memory, by the whole block;
+// z, c and the result in LDS (tmp holds the new vector).
+template <typename T, int D, int NT>
+__device__ __forceinline__ void block_matvec_g(const T* M, const T* c, T* z, T* tmp, bool payload) {
+  constexpr int QC = (D * 2 <= NT) ? ((D * 4 <= NT) ? 4 : 2) : 1;
+  static_assert(D % QC == 0, "split");
+  const int tid = threadIdx.x, i = tid / QC, q = tid % QC;
+  T part = T(0);
+  if (i < D) {
+    const T* row = M + (int64_t)i * D + q * (D / QC);
+    for (int k = 0; k < D / QC; k++)
+      part += (payload ? ld_payload(row + k) : row[k]) * z[q * (D / QC) + k];
+  }
+#pragma unroll
+  for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
+  if (i < D && q == 0) tmp[i] = part + (payload ? ld_payload(c + i) : c[i]);
+  __syncthreads();
+  if (tid < D) z[tid] = tmp[tid];
+  __syncthreads();
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
+  using SH = DenseScanShape<D>;
+  using MF = Mfma<T>;
+  constexpr int DP = SH::DP, NTL = SH::NTL, PS = SH::PS, NT = SH::NT, RT = SH::RT;
+  constexpr int E = D * D + D;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sP = reinterpret_cast<T*>(smem_raw);          // running product, DP x PS
+  T* sq = sP + DP * PS;                             // running b-part
+  T* sz = sq + DP;                                  // z vector
+  T* st = sz + DP;                                  // scratch vector
+  __shared__ uint32_t s_tile;
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  if (tid == 0) s_tile = atomicAdd(a.counter, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t seq = tile / a.tiles_per_seq, ts = tile % a.tiles_per_seq;
+  const int64_t e0 = ts * (int64_t)a.L;
+  const int n_el = (int)((a.N - e0) < a.L ? (a.N - e0) : a.L);
+  const T* Aseq = static_cast<const T*>(a.A) + (seq * a.N + e0) * D * D;
+  const T* bseq = static_cast<const T*>(a.b) + (seq * a.N + e0) * D;
+
+  // P <- A_0 (zero padded), q <- b_0
+  for (int idx = tid; idx < DP * DP; idx += NT) {
+    const int i = idx / DP, j = idx % DP;
+    sP[i * PS + j] = (i < D && j < D) ? Aseq[i * D + j] : T(0);
+  }
+  for (int i = tid; i < DP; i += NT) sq[i] = i < D ? bseq[i] : T(0);
+  __syncthreads();
+
+  // fold the remaining elements: (P, q) <- (A_m P, A_m q + b_m)
+  for (int m = 1; m < n_el; m++) {
+    const T* Am = Aseq + (int64_t)m * D * D;
+    typename MF::acc_t acc[RT][NTL];
+#pragma unroll
+    for (int r = 0; r < RT; r++)
+#pragma unroll
+      for (int c = 0; c < NTL; c++) acc[r][c] = typename MF::acc_t{};
+#pragma unroll 2
+    for (int kk = 0; kk < DP / 4; kk++) {
+      const int k = kk * 4 + lane / 16;
+      T av[RT];
+#pragma unroll
+      for (int r = 0; r < RT; r++) {
+        const int rt = wv + r * SH::NW;
+        const int i = rt * 16 + lane % 16;
+        av[r] = (rt < NTL && i < D && k < D) ? Am[i * D + k] : T(0);
+      }
+#pragma unroll
+      for (int c = 0; c < NTL; c++) {
+        const T bv = sP[k * PS + c * 16 + lane % 16];
+#pragma unroll
+        for (int r = 0; r < RT; r++)
+          if (wv + r * SH::NW < NTL) acc[r][c] = MF::mma(av[r], bv, acc[r][c]);
+      }
+    }
+    // q_new = A_m q + b_m (uses the old q, before P and q are overwritten)
+    {
+      constexpr int QC = (D * 2 <= NT) ? ((D * 4 <= NT) ? 4 : 2) : 1;
+      const int i = tid / QC, q = tid % QC;
+      T part = T(0);
+      if (i < D)
+        for (int k = 0; k < D / QC; k++) part += Am[(int64_t)i * D + q * (D / QC) + k] * sq[q * (D / QC) + k];
+#pragma unroll
+      for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
+      if (i < D && q == 0) st[i] = part + bseq[(int64_t)m * D + i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RT; r++) {
+      const int rt = wv + r * SH::NW;
+      if (rt < NTL)
+#pragma unroll
+        for (int c = 0; c < NTL; c++)
+#pragma unroll
+          for (int v = 0; v < 4; v++) sP[(rt * 16 + MF::row(lane, v)) * PS + c * 16 + lane % 16] = acc[r][c][v];
+    }
+    if (tid < D) sq[tid] = st[tid];
+    __syncthreads();
+  }
+
+  // lookback for z at the start of the tile
+  const int64_t base = seq * a.tiles_per_seq;
+  uint32_t* flags = a.flags + base;
+  T* aggp = static_cast<T*>(a.agg) + base * E;
+  T* inclp = static_cast<T*>(a.incl) + base * D;
+  __shared__ int64_t s_j;
+  if (ts == 0) {
+    for (int i = tid; i < D; i += NT) sz[i] = a.z0 ? static_cast<const T*>(a.z0)[seq * D + i] : T(0);
+    __syncthreads();
+  } else {
+    for (int idx = tid; idx < D * D; idx += NT) aggp[ts * E + idx] = sP[(idx / D) * PS + idx % D];
+    for (int i = tid; i < D; i += NT) aggp[ts * E + D * D + i] = sq[i];
+    __syncthreads();
+    if (tid == 0) {
+      publish_flag(flags + ts, FLAG_AGG);
+      int64_t j = ts - 1;
+      for (;;) {
+        const uint32_t f = wait_flag(flags + j, a.err);
+        if (f == FLAG_INCL || f == 0) break;
+        j--;
+      }
+      s_j = j;
+    }
+    __syncthreads();
+    const int64_t j = s_j;
+    for (int i = tid; i < D; i += NT) sz[i] = ld_payload(inclp + j * D + i);
+    __syncthreads();
+    for (int64_t mm = j + 1; mm < ts; mm++)
+      block_matvec_g<T, D, NT>(aggp + mm * E, aggp + mm * E + D * D, sz, st, true);
+  }
+  // publish this tile's inclusive prefix: P z_in + q
+  {
+    constexpr int QC = (D * 2 <= NT) ? ((D * 4 <= NT) ? 4 : 2) : 1;
+    const int i = tid / QC, q = tid % QC;
+    T part = T(0);
+    if (i < D)
+      for (int k = 0; k < D / QC; k++) part += sP[i * PS + q * (D / QC) + k] * sz[q * (D / QC) + k];
+#pragma unroll
+    for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
+    if (i < D && q == 0) inclp[ts * D + i] = part + sq[i];
+    __syncthreads();
+    if (tid == 0) publish_flag(flags + ts, FLAG_INCL);
+  }
+
+  // outputs: z_{e0+m+1} = A_m z + b_m in order
+  T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
+  for (int m = 0; m < n_el; m++) {
+    block_matvec_g<T, D, NT>(Aseq + (int64_t)m * D * D, bseq + (int64_t)m * D, sz, st, false);
+    for (int i = tid; i < D; i += NT) zg[(int64_t)m * D + i] = sz[i];
+  }
+}
+
+// ------------------------------------------------------------- host -------
+
+static int scan_tile_elems(int d, int dtype, int tile) {
+  if (d <= 8) {
+    switch (d) {
+#define PINT_SMALL_TILE(DD)                                                               \
+  case DD:                                                                                \
+    return dtype == 0 ? small_nt<DD, double>() * small_s<DD, double>()                    \
+                      : small_nt<DD, float>() * small_s<DD, float>();
+      PINT_SMALL_TILE(1) PINT_SMALL_TILE(2) PINT_SMALL_TILE(3) PINT_SMALL_TILE(4)
+      PINT_SMALL_TILE(5) PINT_SMALL_TILE(6) PINT_SMALL_TILE(7) PINT_SMALL_TILE(8)
+#undef PINT_SMALL_TILE
+    }
+    return 0;
+  }
+  return tile > 0 ? tile : 16;
+}
+
+static bool scan_dense_d(int d) { return d == 16 || d == 32 || d == 40 || d == 64 || d == 128; }
+
+size_t scan_ws_bytes(int d, int64_t B, int64_t N, int tile, int dtype) {
+  if (d < 1 || B < 0 || N < 0) return 0;
+  if (d > 8 && !scan_dense_d(d)) return 0;
+  const int L = scan_tile_elems(d, dtype, tile);
+  if (L <= 0) return 0;
+  const int64_t tps = (N + L - 1) / L;
+  const int64_t nt = B * tps;
+  const size_t s = dtype == 0 ? 8 : 4;
+  return 256 + align_up((size_t)nt * 4) + align_up((size_t)nt * (d * d + d) * s) +
+         align_up((size_t)nt * d * s);
+}
+
+template <typename T, int D>
+static int launch_small(const ScanArgs& sa, int64_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_scan_small<T, D>), dim3((unsigned)grid), dim3(small_nt<D, T>()), 0, s, sa);
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
+}
+
+template <typename T, int D>
+static int launch_dense(const ScanArgs& sa, int64_t grid, hipStream_t s) {
+  const size_t lds = dense_scan_lds<T, D>();
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_dense<T, D>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return ST_DEVICE;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_scan_dense<T, D>), dim3((unsigned)grid), dim3(256), lds, s, sa);
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
+}
+
+int affine_scan(int d, int64_t B, int64_t N, int dtype, const void* A, const void* b,
+                const void* z0, void* z, int tile, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (d > 8 && !scan_dense_d(d)) return ST_UNSUPPORTED;
+  if (dtype != 0 && dtype != 1) return ST_INVALID;
+  const size_t need = scan_ws_bytes(d, B, N, tile, dtype);
+  if (!ws || ws_bytes < need) return ST_WORKSPACE;
+  const int L = scan_tile_elems(d, dtype, tile);
+  const int64_t tps = (N + L - 1) / L;
+  const int64_t nt = B * tps;
+  if (nt > 0x7fffffffLL) return ST_INVALID;
+  const size_t sz = dtype == 0 ? 8 : 4;
+  char* w = static_cast<char*>(ws);
+  ScanArgs sa{};
+  sa.B = B;
+  sa.N = N;
+  sa.tiles_per_seq = tps;
+  sa.L = L;
+  sa.A = A;
+  sa.b = b;
+  sa.z0 = z0;
+  sa.z = z;
+  sa.counter = reinterpret_cast<uint32_t*>(w);
+  sa.err = reinterpret_cast<uint32_t*>(w) + 1;
+  sa.flags = reinterpret_cast<uint32_t*>(w + 256);
+  sa.agg = w + 256 + align_up((size_t)nt * 4);
+  sa.incl = w + 256 + align_up((size_t)nt * 4) + align_up((size_t)nt * (d * d + d) * sz);
+  // reset the tile counter, error word and flags (a kernel, not a memset)
+  if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w), 64 + (size_t)nt, 0u, s)) return rc;
+#define PINT_CASE_SMALL(DD) \
+  case DD: return dtype == 0 ? launch_small<double, DD>(sa, nt, s) : launch_small<float, DD>(sa, nt, s);
+#define PINT_CASE_DENSE(DD) \
+  case DD: return dtype == 0 ? launch_dense<double, DD>(sa, nt, s) : launch_dense<float, DD>(sa, nt, s);
+  switch (d) {
+    PINT_CASE_SMALL(1) PINT_CASE_SMALL(2) PINT_CASE_SMALL(3) PINT_CASE_SMALL(4)
+    PINT_CASE_SMALL(5) PINT_CASE_SMALL(6) PINT_CASE_SMALL(7) PINT_CASE_SMALL(8)
+    PINT_CASE_DENSE(16) PINT_CASE_DENSE(32) PINT_CASE_DENSE(40) PINT_CASE_DENSE(64)
+    PINT_CASE_DENSE(128)
+  }
+#undef PINT_CASE_SMALL
+#undef PINT_CASE_DENSE
+  return ST_UNSUPPORTED;
+}
+
+}  // namespace pint

@@ -1,0 +1,83 @@
+"""GPU parity of the decoupled-lookback affine scan (pint_affine_scan) against
+the oracle's sequential recursion z_{n+1} = A_n z_n + b_n, element by
+element.  Elements are orthogonal maps (products of Givens rotations) so long
+prefixes stay bounded and exactly checkable; FP64 bar 1e-11 relative to the
+largest |z|, FP32 bar 1e-4 relative."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+# elements per tile of the small-d kernel (FP64): 256 threads x S elements
+SMALL_TILE = {1: 3072, 2: 1024, 3: 512, 4: 256, 8: 64}
+
+
+def _ref(orc, A, b, z0):
+    return np.stack([orc.affine_seq(A[s], b[s], None if z0 is None else z0[s]) for s in range(A.shape[0])])
+
+
+def _check(pint, orc, d, N, B, dtype, with_z0, seed, tile=0):
+    A = np.empty((B, N, d, d))
+    b = np.empty((B, N, d))
+    for s in range(B):
+        A[s], b[s] = W.random_affine(N, d, seed=seed + s, kind="rotation")
+    z0 = np.random.default_rng(seed).normal(size=(B, d)) if with_z0 else None
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    At, bt = torch.tensor(A, dtype=tdt, device=DEV), torch.tensor(b, dtype=tdt, device=DEV)
+    z0t = None if z0 is None else torch.tensor(z0, dtype=tdt, device=DEV)
+    z = pint.affine_scan(At, bt, z0t, tile=tile)
+    torch.cuda.synchronize()
+    if dtype == "f32":
+        A, b = A.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)
+        z0 = None if z0 is None else z0.astype(np.float32).astype(np.float64)
+    ref = _ref(orc, A, b, z0)
+    got = z.double().cpu().numpy()
+    scale = max(1.0, np.abs(ref).max())
+    err = np.abs(got - ref).max() / scale
+    assert err <= (1e-11 if dtype == "f64" else 1e-4), (d, N, B, dtype, err)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 8])
+def test_small_d_several_tiles_ragged(pint, orc, d, dtype):
+    tile = SMALL_TILE[d] if dtype == "f64" else None
+    N = 3 * (tile or SMALL_TILE[d]) + 17
+    print(f"[scan] d={d} {dtype} N={N}", flush=True)
+    _check(pint, orc, d, N, 3, dtype, True, seed=10 + d)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("d", [16, 40, 128])
+def test_dense_d_several_tiles_ragged(pint, orc, d, dtype):
+    N = 16 * 5 + 3
+    print(f"[scan] d={d} {dtype} N={N}", flush=True)
+    _check(pint, orc, d, N, 2, dtype, True, seed=20 + d)
+
+
+@pytest.mark.parametrize("d,N", [(3, 1), (3, 512), (40, 1), (40, 16), (40, 17), (2, 2)])
+def test_edge_lengths(pint, orc, d, N):
+    _check(pint, orc, d, N, 2, "f64", False, seed=5)
+
+
+def test_dense_tile_sizes(pint, orc):
+    for tile in (1, 3, 32):
+        _check(pint, orc, 40, 70, 1, "f64", True, seed=7, tile=tile)
+
+
+def test_long_sequence(pint, orc):
+    """2^20 elements of d = 3: hundreds of tiles in flight at once."""
+    _check(pint, orc, 3, 1 << 20, 1, "f64", True, seed=3)
+
+
+def test_empty_and_errors(pint):
+    A = torch.zeros((1, 0, 3, 3), dtype=torch.float64, device=DEV)
+    b = torch.zeros((1, 0, 3), dtype=torch.float64, device=DEV)
+    assert pint.affine_scan(A, b).shape == (1, 0, 3)
+    A = torch.zeros((1, 4, 9, 9), dtype=torch.float64, device=DEV)   # d = 9 is not built
+    b = torch.zeros((1, 4, 9), dtype=torch.float64, device=DEV)
+    with pytest.raises(pint.PintError):
+        pint.affine_scan(A, b)
