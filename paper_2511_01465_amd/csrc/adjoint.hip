@@ -1,0 +1,363 @@
+// Reverse-time adjoint of the discrete solution map x_n = Phi(x_{n-1}; theta):
+// H^T lambda = g for the block-bidiagonal H of eq. (jacobian), i.e.
+//   lambda_T = g_T,  lambda_n = g_n + J(x_n)^T lambda_{n+1},
+// evaluated with the affine scan over the reversed, transposed elements
+//   e_0 = (., g_T),  e_i = (J(x_{T-i})^T, g_{T-i}) for 1 <= i < T,
+//   e_T = (J(x_0)^T, 0),
+// so that scan output i is lambda_{T-i} and output T is dL/dx0.  Elements are
+// recomputed from the trajectory segment by segment when `seg` > 0 (memory
+// seg*d*d per instance instead of T*d*d).  dL/dtheta = sum_n S(x_{n-1})^T
+// lambda_n with S = dPhi/dtheta, reduced with atomics.
+#include <type_traits>
+
+#include "internal.h"
+#include "systems_dense.h"
+#include "systems_small.h"
+
+namespace pint {
+
+struct AdjArgs {
+  int64_t B, T;
+  const void* x0;
+  const void* params;
+  int64_t pstride;
+  const void* traj;
+  const void* g;
+  double dt;
+  int64_t i_lo, i_hi;  // element range [i_lo, i_hi) of this segment
+  void* A;             // [B][i_hi-i_lo][D][D]  (row-major J^T)
+  void* b;             // [B][i_hi-i_lo][D]
+};
+
+// state index of element i: x_{T-i} for 1 <= i < T, x_0 for i = T (n = 0)
+__device__ __forceinline__ int64_t adj_state(int64_t T, int64_t i) { return i == T ? 0 : T - i; }
+
+template <typename T, class S>
+__global__ void k_adj_elems_small(AdjArgs a) {
+  constexpr int D = S::D, NP = S::NP;
+  const int64_t L = a.i_hi - a.i_lo, total = a.B * L;
+  for (int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gi < total;
+       gi += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t inst = gi / L, i = a.i_lo + gi % L;
+    T* Ao = static_cast<T*>(a.A) + gi * D * D;
+    T* bo = static_cast<T*>(a.b) + gi * D;
+    const T* G = static_cast<const T*>(a.g) + inst * a.T * D;
+    if (i == 0) {
+#pragma unroll
+      for (int r = 0; r < D * D; r++) Ao[r] = (r / D == r % D) ? T(1) : T(0);
+#pragma unroll
+      for (int r = 0; r < D; r++) bo[r] = G[(a.T - 1) * D + r];
+      continue;
+    }
+    const int64_t n = adj_state(a.T, i);
+    const T* X = static_cast<const T*>(a.traj) + inst * a.T * D;
+    const T* x0 = static_cast<const T*>(a.x0) + inst * D;
+    T P[NP], x[D], phi[D], J[D * D];
+    const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
+#pragma unroll
+    for (int r = 0; r < NP; r++) P[r] = Pg[r];
+#pragma unroll
+    for (int r = 0; r < D; r++) x[r] = n == 0 ? x0[r] : X[(n - 1) * D + r];
+    rk4_phi_jac<T, S>(P, (T)a.dt, x, phi, J);
+#pragma unroll
+    for (int r = 0; r < D; r++)
+#pragma unroll
+      for (int c = 0; c < D; c++) Ao[r * D + c] = J[c * D + r];
+#pragma unroll
+    for (int r = 0; r < D; r++) bo[r] = (i == a.T) ? T(0) : G[(n - 1) * D + r];
+  }
+}
+
+template <typename T, class S>
+__global__ __launch_bounds__(S::NT) void k_adj_elems_dense(AdjArgs a) {
+  constexpr int D = S::D, NP = S::NP, NT = S::NT, NW = NT / PINT_WAVE, SPP = S::SPP, JT = S::JT;
+  __shared__ typename S::Stage s_stage[SPP];
+  __shared__ T s_P[SPP][NP];
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  const int64_t L = a.i_hi - a.i_lo, total = a.B * L;
+  const int64_t g0 = (int64_t)blockIdx.x * SPP;
+  for (int sl = 0; sl < SPP; sl++) {
+    const int64_t gi = g0 + sl;
+    if (gi < total) {
+      const T* P = static_cast<const T*>(a.params) + (gi / L) * a.pstride;
+      for (int r = tid; r < NP; r += NT) s_P[sl][r] = P[r];
+    }
+  }
+  __syncthreads();
+  for (int sl = wv; sl < SPP; sl += NW) {
+    const int64_t gi = g0 + sl;
+    if (gi >= total) continue;
+    const int64_t inst = gi / L, i = a.i_lo + gi % L;
+    const T* G = static_cast<const T*>(a.g) + inst * a.T * D;
+    T* bo = static_cast<T*>(a.b) + gi * D;
+    const int64_t n = adj_state(a.T, i);
+    if (i == 0) {
+      for (int r = lane; r < D; r += PINT_WAVE) bo[r] = G[(a.T - 1) * D + r];
+      continue;
+    }
+    for (int r = lane; r < D; r += PINT_WAVE) bo[r] = (i == a.T) ? T(0) : G[(n - 1) * D + r];
+    const T* X = static_cast<const T*>(a.traj) + inst * a.T * D;
+    const T* x0 = static_cast<const T*>(a.x0) + inst * D;
+    T xp[S::R], phi[S::R];
+#pragma unroll
+    for (int r = 0; r < S::R; r++) {
+      const int c = lane + 64 * r;
+      xp[r] = c < D ? (n == 0 ? x0[c] : X[(n - 1) * D + c]) : T(0);
+    }
+    wave_rk4<T, S>(s_P[sl], (T)a.dt, xp, phi, &s_stage[sl], lane);
+  }
+  __syncthreads();
+  for (int t = tid; t < SPP * JT; t += NT) {
+    const int sl = t / JT, sub = t % JT;
+    const int64_t gi = g0 + sl;
+    if (gi >= total) continue;
+    const int64_t i = a.i_lo + gi % L;
+    T* Ao = static_cast<T*>(a.A) + gi * D * D;
+    if (i == 0) {
+      // identity (multiplies z_0 = 0)
+      if (sub == 0)
+        for (int r = 0; r < D * D; r++) Ao[r] = (r / D == r % D) ? T(1) : T(0);
+      continue;
+    }
+    // J(i, j) -> Ao[j * D + i]: the row-major transpose
+    S::jac_thread(&s_stage[sl], s_P[sl], sub, (T)a.dt, Ao, 1, D);
+  }
+}
+
+// Copy this segment's scan outputs into lambda [B][T+1][D] and keep the
+// last one as the next segment's starting vector.
+template <typename T>
+__global__ void k_adj_copy(int64_t B, int64_t T1, int64_t i_lo, int64_t L, int D, const T* zs,
+                           T* lam, T* carry) {
+  const int64_t total = B * L * D;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t inst = g / (L * D), rem = g % (L * D), m = rem / D, c = rem % D;
+    const T v = zs[g];
+    lam[(inst * T1 + i_lo + m) * D + c] = v;
+    if (m == L - 1) carry[inst * D + c] = v;
+  }
+}
+
+// dL/dtheta += S(x_{n-1})^T lambda_n, lambda_n = lam[T - n], n = 1..T.
+template <typename T, class S>
+__global__ void k_adj_theta_small(AdjArgs a, const T* lam, T* dth) {
+  constexpr int D = S::D, NP = S::NP;
+  const int64_t total = a.B * a.T;
+  for (int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gi < total;
+       gi += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t inst = gi / a.T, n = gi % a.T + 1;
+    const T* X = static_cast<const T*>(a.traj) + inst * a.T * D;
+    const T* x0 = static_cast<const T*>(a.x0) + inst * D;
+    T P[NP], x[D], J[D * D], Sth[D * NP];
+    const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
+#pragma unroll
+    for (int r = 0; r < NP; r++) P[r] = Pg[r];
+#pragma unroll
+    for (int r = 0; r < D; r++) x[r] = n == 1 ? x0[r] : X[(n - 2) * D + r];
+    rk4_jac_ptheta<T, S>(P, (T)a.dt, x, J, Sth);
+    const T* ln = lam + (inst * (a.T + 1) + (a.T - n)) * D;
+#pragma unroll
+    for (int j = 0; j < NP; j++) {
+      T acc = T(0);
+#pragma unroll
+      for (int r = 0; r < D; r++) acc += Sth[r * NP + j] * ln[r];
+      atomicAdd(dth + inst * NP + j, acc);
+    }
+  }
+}
+
+// Lorenz-96: theta = F, S = dPhi/dF by the chain rule through the stages
+// (f_F = 1):  D1 = 1, D_s = Jf(x_s)(c D_{s-1}) + 1, S = dt/6 (D1+2D2+2D3+D4).
+// One wave per step; the stencil product by shuffles.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_adj_theta_l96(AdjArgs a, const T* lam, T* dth) {
+  using S = DSysL96<T, DIM>;
+  constexpr int D = DIM;
+  const int lane = threadIdx.x % 64;
+  const int64_t gi = blockIdx.x * 4 + threadIdx.x / 64;
+  if (gi >= a.B * a.T) return;
+  const int64_t inst = gi / a.T, n = gi % a.T + 1;
+  const T* X = static_cast<const T*>(a.traj) + inst * a.T * D;
+  const T* x0 = static_cast<const T*>(a.x0) + inst * D;
+  const T* P = static_cast<const T*>(a.params) + inst * a.pstride;
+  const int i = lane < D ? lane : 0;
+  const T dt = (T)a.dt, h2 = T(0.5) * dt, c6 = dt / T(6);
+  T x[1] = {lane < D ? (n == 1 ? x0[i] : X[(n - 2) * D + i]) : T(0)};
+  T k[1], y[1] = {x[0]};
+  T Dv = T(1), acc = T(1);
+  S::f(P, x, k, lane);
+  for (int s = 1; s < 4; s++) {
+    const T cprev = (s == 3) ? dt : h2;   // x_{s+1} = x + c k_s
+    y[0] = x[0] + cprev * k[0];
+    // Jf(y) (cprev * Dv) + 1
+    const T v = cprev * Dv;
+    const T yp1 = __shfl(y[0], (i + 1) % D, 64), ym1 = __shfl(y[0], (i + D - 1) % D, 64);
+    const T ym2 = __shfl(y[0], (i + D - 2) % D, 64);
+    const T vp1 = __shfl(v, (i + 1) % D, 64), vm1 = __shfl(v, (i + D - 1) % D, 64);
+    const T vm2 = __shfl(v, (i + D - 2) % D, 64);
+    Dv = ym1 * (vp1 - vm2) + (yp1 - ym2) * vm1 - v + T(1);
+    acc += ((s == 3) ? T(1) : T(2)) * Dv;
+    S::f(P, y, k, lane);
+  }
+  const T Sv = c6 * acc;
+  const T* ln = lam + (inst * (a.T + 1) + (a.T - n)) * D;
+  T part = lane < D ? Sv * ln[i] : T(0);
+  part = wave_sum(part);
+  if (lane == 0) atomicAdd(dth + inst, part);
+}
+
+// ------------------------------------------------------------- host -------
+
+template <typename F>
+static int dispatch_adj(int dtype, int system, int d, F&& f) {
+  auto go = [&](auto t) -> int {
+    using T = decltype(t);
+    switch (system) {
+      case 0:
+        switch (d) {
+          case 1: return f(t, SysLinear<T, 1>{}, std::true_type{});
+          case 2: return f(t, SysLinear<T, 2>{}, std::true_type{});
+          case 3: return f(t, SysLinear<T, 3>{}, std::true_type{});
+          case 4: return f(t, SysLinear<T, 4>{}, std::true_type{});
+        }
+        break;
+      case 1: if (d == 1) return f(t, SysLogistic<T>{}, std::true_type{}); break;
+      case 2: if (d == 2) return f(t, SysVdP<T>{}, std::true_type{}); break;
+      case 3: if (d == 4) return f(t, SysCartPole<T>{}, std::true_type{}); break;
+      case 4: if (d == 3) return f(t, SysLorenz63<T>{}, std::true_type{}); break;
+      case 5: if (d == 40) return f(t, DSysL96<T, 40>{}, std::false_type{}); break;
+      case 6:
+        if (d == 128) return f(t, DSysKur<T, 128>{}, std::false_type{});
+        if (d == 64) return f(t, DSysKur<T, 64>{}, std::false_type{});
+        break;
+    }
+    return ST_UNSUPPORTED;
+  };
+  if (dtype == 0) return go((double)0);
+  if (dtype == 1) return go((float)0);
+  return ST_UNSUPPORTED;
+}
+
+struct AdjLayout {
+  int64_t L;  // elements per segment
+  size_t off_A, off_b, off_lam, off_zs, off_carry, off_scan, scan_bytes, total;
+};
+
+static AdjLayout adj_layout(int d, int64_t B, int64_t T, int64_t seg, int dtype) {
+  AdjLayout l{};
+  const size_t s = dtype == 0 ? 8 : 4;
+  const int64_t T1 = T + 1;
+  l.L = (seg > 0 && seg < T1) ? seg : T1;
+  size_t o = 0;
+  l.off_A = o;     o += align_up((size_t)B * l.L * d * d * s);
+  l.off_b = o;     o += align_up((size_t)B * l.L * d * s);
+  l.off_lam = o;   o += align_up((size_t)B * T1 * d * s);
+  l.off_zs = o;    o += align_up((size_t)B * l.L * d * s);
+  l.off_carry = o; o += align_up((size_t)B * d * s);
+  l.off_scan = o;
+  l.scan_bytes = scan_ws_bytes(d, B, l.L, 0, dtype);
+  o += align_up(l.scan_bytes);
+  l.total = o;
+  return l;
+}
+
+size_t adjoint_ws_bytes(int system, int d, int64_t B, int64_t T, int64_t seg, int dtype) {
+  if (!small_supported(system, d) && !dense_supported(system, d)) return 0;
+  return adj_layout(d, B, T, seg, dtype).total;
+}
+
+int adjoint(const SolveArgs& sa, const void* g, void* dL_dx0, void* dL_dth, int64_t seg) {
+  const int d = sa.d;
+  const int64_t B = sa.B, T = sa.T_uniform, T1 = T + 1;
+  if (sa.system == 6 && dL_dth) return ST_UNSUPPORTED;  // Kuramoto: dL/dx0 only
+  const AdjLayout lay = adj_layout(d, B, T, seg, sa.dtype);
+  if (!sa.ws || sa.ws_bytes < lay.total) return ST_WORKSPACE;
+  char* w = static_cast<char*>(sa.ws);
+  hipStream_t st = sa.stream;
+  const size_t s = sa.dtype == 0 ? 8 : 4;
+  int np = 0;
+  switch (sa.system) {
+    case 0: np = d * d; break;   // linear: M
+    case 1: np = 2; break;       // logistic: r, K
+    case 2: np = 1; break;       // van der Pol: mu
+    case 4: np = 3; break;       // Lorenz-63: sigma, rho, beta
+    case 5: np = 1; break;       // Lorenz-96: F
+    default: if (dL_dth) return ST_UNSUPPORTED;
+  }
+  if (dL_dth)
+    if (int rc = fill_u32(static_cast<uint32_t*>(dL_dth), (size_t)B * np * s / 4, 0u, st)) return rc;
+  if (T == 0)  // no loss terms: dL/dx0 = 0
+    return fill_u32(static_cast<uint32_t*>(dL_dx0), (size_t)B * d * s / 4, 0u, st);
+  return dispatch_adj(sa.dtype, sa.system, d, [&](auto t, auto sys, auto is_small) -> int {
+    using T_ = decltype(t);
+    using S = decltype(sys);
+    constexpr int D = S::D;
+    AdjArgs a{};
+    a.B = B;
+    a.T = T;
+    a.x0 = sa.x0;
+    a.params = sa.params;
+    a.pstride = sa.pstride;
+    a.traj = sa.traj;
+    a.g = g;
+    a.dt = sa.dt;
+    a.A = w + lay.off_A;
+    a.b = w + lay.off_b;
+    T_* lam = reinterpret_cast<T_*>(w + lay.off_lam);
+    T_* zs = reinterpret_cast<T_*>(w + lay.off_zs);
+    T_* carry = reinterpret_cast<T_*>(w + lay.off_carry);
+    const bool segmented = lay.L < T1;
+    for (int64_t lo = 0; lo < T1; lo += lay.L) {
+      const int64_t hi = lo + lay.L < T1 ? lo + lay.L : T1, L = hi - lo;
+      a.i_lo = lo;
+      a.i_hi = hi;
+      const int64_t tot = B * L;
+      if constexpr (decltype(is_small)::value) {
+        const int grid = (int)((tot + 255) / 256 < 8192 ? (tot + 255) / 256 : 8192);
+        hipLaunchKernelGGL((k_adj_elems_small<T_, S>), dim3(grid), dim3(256), 0, st, a);
+      } else {
+        const int64_t grid = (tot + S::SPP - 1) / S::SPP;
+        hipLaunchKernelGGL((k_adj_elems_dense<T_, S>), dim3((unsigned)grid), dim3(S::NT), 0, st, a);
+      }
+      if (hipGetLastError() != hipSuccess) return ST_DEVICE;
+      // the scan writes straight into lambda when there is one segment
+      T_* zout = segmented ? zs : lam;
+      // affine_scan needs B sequences of L elements: contiguous in A/b
+      int rc = affine_scan(D, B, L, sa.dtype, a.A, a.b, lo == 0 ? nullptr : carry, zout, 0,
+                           w + lay.off_scan, lay.scan_bytes, st);
+      if (rc) return rc;
+      if (segmented) {
+        const int64_t n = B * L * D;
+        const int grid = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+        hipLaunchKernelGGL((k_adj_copy<T_>), dim3(grid), dim3(256), 0, st, B, T1, lo, L, D,
+                           (const T_*)zs, lam, carry);
+        if (hipGetLastError() != hipSuccess) return ST_DEVICE;
+      }
+    }
+    // dL/dx0 = lambda row T of every instance
+    if (hipMemcpy2DAsync(dL_dx0, D * s, lam + T * D, T1 * D * s, D * s, B, hipMemcpyDeviceToDevice,
+                         st) != hipSuccess)
+      return ST_DEVICE;
+    if (dL_dth) {
+      if constexpr (decltype(is_small)::value) {
+        const int64_t tot = B * T;
+        const int grid = (int)((tot + 255) / 256 < 8192 ? (tot + 255) / 256 : 8192);
+        if (tot > 0)
+          hipLaunchKernelGGL((k_adj_theta_small<T_, S>), dim3(grid), dim3(256), 0, st, a,
+                             (const T_*)lam, static_cast<T_*>(dL_dth));
+      } else if constexpr (D == 40 && S::NP == 1) {
+        const int64_t tot = B * T;
+        if (tot > 0)
+          hipLaunchKernelGGL((k_adj_theta_l96<T_, 40>), dim3((unsigned)((tot + 3) / 4)), dim3(256), 0,
+                             st, a, (const T_*)lam, static_cast<T_*>(dL_dth));
+      } else {
+        return ST_UNSUPPORTED;
+      }
+      if (hipGetLastError() != hipSuccess) return ST_DEVICE;
+    }
+    return ST_OK;
+  });
+}
+
+}  // namespace pint
