@@ -42,6 +42,152 @@ def lorenz96_step_flops(d: int, window: int) -> dict:
     return dict(per_window_step=per_step, per_update=window * per_step + 10 * 50 * d)
 
 
+# ------------------------------------------------------------ extra legs --
+
+def _time(fn, reps, stream):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def leg_scan_small(P, torch, dev, stream, reps=5):
+    """Small-d affine scan alone on 2^24 orthogonal elements per d (HBM bound):
+    algorithmic bytes per element (d^2 + d) * 8 read + d * 8 written."""
+    import workloads as W
+    out = {}
+    N = 1 << 24
+    for d in (2, 3, 4):
+        A = torch.empty((1, N, d, d), dtype=torch.float64, device=dev)
+        b = torch.empty((1, N, d), dtype=torch.float64, device=dev)
+        chunk = 1 << 20
+        for c0 in range(0, N, chunk):
+            Ah, bh = W.random_affine(chunk, d, seed=c0 // chunk, kind="rotation")
+            A[0, c0:c0 + chunk] = torch.from_numpy(Ah)
+            b[0, c0:c0 + chunk] = torch.from_numpy(bh)
+        z = torch.empty((1, N, d), dtype=torch.float64, device=dev)
+        ws = torch.empty(P.pint_scan_workspace_bytes(d, 1, N, 0, P.F64), dtype=torch.uint8, device=dev)
+        ms = _time(lambda: P.pint_affine_scan(d, 1, N, P.F64, A, b, None, z, 0, ws, stream), reps, stream)
+        byt = N * ((d * d + d) * 8 + d * 8)
+        out[f"d{d}"] = {"ms": ms, "GB/s": byt / (ms / 1e3) / 1e9, "frac_hbm": byt / (ms / 1e3) / PEAK_HBM,
+                        "bytes_per_launch": byt, "elements": N}
+        del A, b, z, ws
+        torch.cuda.empty_cache()
+    return out
+
+
+def leg_dense_fullT(P, torch, dev, stream, which, reps=3):
+    """One full-horizon Newton iteration of a dense workload, split into its
+    two kernels: elements (RK4 Jacobians by the chain rule) and the
+    decoupled-lookback scan whose tile aggregates run on FP64 MFMA.
+    Scan algorithmic flops per element: 2 d^3 (composition) + 4 d^2."""
+    import workloads as W
+    if which == "lorenz96":
+        w = W.lorenz96(T=65536)
+    else:
+        w = W.kuramoto()
+    B, T, d = w.B, int(w.T[0]), w.d
+    x0 = torch.tensor(w.x0, device=dev)
+    prm = torch.tensor(w.params, device=dev)
+    # the first Newton iterate: the constant guess x_n = x0
+    traj = x0[:, None, :].expand(B, T, d).contiguous()
+    sysd = P.make_system(w.system, d, prm, False)
+    A = torch.empty((B, T, d, d), dtype=torch.float64, device=dev)
+    b = torch.empty((B, T, d), dtype=torch.float64, device=dev)
+    z = torch.empty((B, T, d), dtype=torch.float64, device=dev)
+    ws = torch.empty(P.pint_scan_workspace_bytes(d, B, T, 0, P.F64), dtype=torch.uint8, device=dev)
+    ms_el = _time(lambda: P.pint_elements(sysd, B, x0, w.dt, T, P.F64, traj, A, b, stream), reps, stream)
+    ms_sc = _time(lambda: P.pint_affine_scan(d, B, T, P.F64, A, b, None, z, 0, ws, stream), reps, stream)
+    n = B * T
+    fl = n * (2 * d ** 3 + 4 * d * d)
+    res = {"elements": n, "elements_ms": ms_el, "scan_ms": ms_sc,
+           "scan_TFLOPs": fl / (ms_sc / 1e3) / 1e12, "scan_frac_fp64_mfma": fl / (ms_sc / 1e3) / PEAK_FP64_VALU,
+           "elements_GB/s_written": n * (d * d + d) * 8 / (ms_el / 1e3) / 1e9,
+           "converged_steps_per_s_if_one_iteration": n / ((ms_el + ms_sc) / 1e3)}
+    del A, b, z, ws, traj
+    torch.cuda.empty_cache()
+    return res
+
+
+def leg_vdp_batch(P, torch, dev, stream, reps=3, window=256):
+    """4096 van der Pol instances, mu ~ U[0.5, 5], T ~ U{256..8192}, one
+    persistent launch, against the one-thread-per-instance sequential RK4."""
+    import workloads as W
+    w = W.vdp_batch(window=window)
+    x0 = torch.tensor(w.x0, device=dev)
+    prm = torch.tensor(w.params, device=dev)
+    lengths = torch.tensor(w.T)
+    total = int(w.T.sum())
+    res = {}
+
+    def run():
+        res["out"] = P.solve_varlen(P.VDP, x0, prm, w.dt, lengths, tol=1e-10, window=window)
+
+    ms = _time(run, reps, stream)
+    traj, T_off, iters, resid, status = res["out"]
+    ms_seq = _time(lambda: P.seq_integrate(P.VDP, x0, prm, w.dt, lengths), reps, stream)
+    return {"instances": w.B, "sum_T": total, "window": window, "ms": ms,
+            "value": total / (ms / 1e3), "all_ok": bool((status == 0).all()),
+            "max_resid": float(resid.max()), "updates_mean": float(iters.double().mean()),
+            "updates_max": int(iters.max()), "sequential_ms": ms_seq,
+            "sequential_value": total / (ms_seq / 1e3), "speedup_of_newton": ms_seq / ms}
+
+
+def leg_adjoint(P, torch, dev, stream, B=256, T=16384, window=32, seg=2048, reps=2):
+    """Adjoint on Lorenz-96 (d=40, T=16384, 256 instances): forward windowed
+    Newton solve, loss over 64 observations, gradients w.r.t. x0 and F by the
+    reverse scan.  grads/s = instances / backward time."""
+    import workloads as W
+    w = W.adjoint_l96(B=B, T=T, window=window)
+    x0 = torch.tensor(w.x0, device=dev)
+    prm = torch.tensor(w.params, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    traj, iters, resid, status = P.solve(P.LORENZ96, x0, prm, w.dt, T, tol=1e-10, window=window)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1)
+    obs = torch.tensor(w.extra["obs"] - 1, device=dev)
+    y = torch.tensor(w.extra["y"], device=dev)
+    g = torch.zeros_like(traj)
+    g[:, obs, :] = 2 * (traj[:, obs, :] - y)
+    res = {}
+
+    def back():
+        res["g"] = P.adjoint(P.LORENZ96, x0, prm, w.dt, traj, g, seg=seg)
+
+    ms = _time(back, reps, stream)
+    return {"instances": B, "T": T, "forward_ms": fwd_ms, "forward_all_ok": bool((status == 0).all()),
+            "backward_ms": ms, "grads_per_s": B / (ms / 1e3), "segment": seg,
+            "fwd_plus_bwd_grads_per_s": B / ((ms + fwd_ms) / 1e3)}
+
+
+def leg_kuramoto(P, torch, dev, stream, window=256, reps=2):
+    import workloads as W
+    w = W.kuramoto(window=window)
+    x0 = torch.tensor(w.x0, device=dev)
+    prm = torch.tensor(w.params, device=dev)
+    T = int(w.T[0])
+    res = {}
+
+    def run():
+        res["o"] = P.solve(P.KURAMOTO, x0, prm, w.dt, T, tol=1e-10, window=window)
+
+    ms = _time(run, reps, stream)
+    traj, iters, resid, status = res["o"]
+    T_off = torch.arange(0, (w.B + 1) * T, T, dtype=torch.int64)
+    ms_seq = _time(lambda: P.seq_integrate(P.KURAMOTO, x0, prm, w.dt, T), reps, stream)
+    return {"instances": w.B, "T": T, "window": window, "ms": ms, "value": w.B * T / (ms / 1e3),
+            "all_ok": bool((status == 0).all()), "updates_max": int(iters.max()),
+            "sequential_ms": ms_seq, "speedup_of_newton": ms_seq / ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +198,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=3072, help="oracle prefix length (steps)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and comparator legs")
+    ap.add_argument("--legs", default="scan,dense,vdp,adjoint,kuramoto",
+                    help="extra workloads to measure (comma list, or 'none')")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -162,6 +310,22 @@ def main():
         except Exception:
             pass
         extra["fp32"] = fp32
+
+    legs = [] if args.legs in ("", "none") else args.legs.split(",")
+    for leg in legs:
+        print(f"[bench] leg {leg}", file=sys.stderr, flush=True)
+        if leg == "scan":
+            extra["scan_small_d"] = leg_scan_small(P, torch, dev, stream)
+        elif leg == "dense":
+            extra["dense_fullT_lorenz96"] = leg_dense_fullT(P, torch, dev, stream, "lorenz96")
+            extra["dense_fullT_kuramoto"] = leg_dense_fullT(P, torch, dev, stream, "kuramoto")
+        elif leg == "vdp":
+            extra["vdp_batch"] = leg_vdp_batch(P, torch, dev, stream)
+        elif leg == "adjoint":
+            extra["adjoint_lorenz96"] = leg_adjoint(P, torch, dev, stream)
+        elif leg == "kuramoto":
+            extra["kuramoto"] = leg_kuramoto(P, torch, dev, stream)
+        print(f"[bench] leg {leg} done", file=sys.stderr, flush=True)
 
     flops = lorenz96_step_flops(d, args.window)
     alg_flops = n_iter * flops["per_update"]

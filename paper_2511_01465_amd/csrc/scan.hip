@@ -61,6 +61,38 @@ __device__ __forceinline__ uint32_t wait_flag(const uint32_t* f, uint32_t* err) 
   }
 }
 
+
+// Wave-parallel lookback search (all 64 lanes of one wave call it): lanes
+// read the flags of predecessors end, end-1, ..., end-63 at once.  Returns,
+// in every lane, the number k of aggregate-only predecessors directly before
+// the first inclusive one within the window (k = 64: none inclusive yet, all
+// 64 aggregates), after waiting until no predecessor in front of the first
+// inclusive one is still unpublished.  `f_out` receives this lane's flag.
+__device__ __forceinline__ int lookback_window(const uint32_t* flags, int64_t end, uint32_t* err,
+                                               uint32_t& f_out) {
+  const int lane = threadIdx.x % PINT_WAVE;
+  const int64_t idx = end - lane;
+  for (uint64_t it = 0;; it++) {
+    const uint32_t f = idx >= 0 ? __hip_atomic_load(flags + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : FLAG_INCL;
+    const uint64_t incl = __ballot(f == FLAG_INCL);
+    const uint64_t zero = __ballot(f == 0);
+    const int first = incl ? __ffsll((long long)incl) - 1 : PINT_WAVE;
+    const uint64_t before = first >= PINT_WAVE ? ~0ull : ((1ull << first) - 1);
+    if (!(zero & before)) {
+      __threadfence();  // acquire: payload reads below see the publishers' data
+      f_out = f;
+      return first;
+    }
+    if (it > SPIN_LIMIT) {
+      if (lane == 0) atomicOr(err, 1u);
+      f_out = FLAG_INCL;
+      return first;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_payload(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -122,8 +154,8 @@ __global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
   if (tid == NT - 1) s_tagg = agg;
   __syncthreads();
 
-  // lookback: z at the start of this tile
-  if (tid == 0) {
+  // lookback by wave 0: z at the start of this tile
+  if (wv == 0) {
     const int64_t base = seq * a.tiles_per_seq;
     uint32_t* flags = a.flags + base;
     T* aggp = static_cast<T*>(a.agg) + base * E;
@@ -133,43 +165,76 @@ __global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
 #pragma unroll
       for (int i = 0; i < D; i++) z[i] = a.z0 ? static_cast<const T*>(a.z0)[seq * D + i] : T(0);
     } else {
+      if (lane == 0) {
 #pragma unroll
-      for (int i = 0; i < D * D; i++) aggp[ts * E + i] = s_tagg.A[i];
+        for (int i = 0; i < D * D; i++) aggp[ts * E + i] = s_tagg.A[i];
 #pragma unroll
-      for (int i = 0; i < D; i++) aggp[ts * E + D * D + i] = s_tagg.b[i];
-      publish_flag(flags + ts, FLAG_AGG);
-      int64_t j = ts - 1;
-      for (;;) {
-        const uint32_t f = wait_flag(flags + j, a.err);
-        if (f == FLAG_INCL || f == 0) break;
-        j--;
+        for (int i = 0; i < D; i++) aggp[ts * E + D * D + i] = s_tagg.b[i];
+        publish_flag(flags + ts, FLAG_AGG);
       }
+      // acc = composition of the aggregates passed so far (newest applied last)
+      Aff<T, D> acc;
+      aff_identity(acc);
+      int64_t end = ts - 1;
+      for (;;) {
+        uint32_t f;
+        const int k = lookback_window(flags, end, a.err, f);
+        // this lane's aggregate if it lies before the first inclusive lane
+        Aff<T, D> v;
+        const int64_t idx = end - lane;
+        if (lane < k) {
 #pragma unroll
-      for (int i = 0; i < D; i++) z[i] = ld_payload(inclp + j * D + i);
-      for (int64_t m = j + 1; m < ts; m++) {
-        T t[D];
+          for (int i = 0; i < D * D; i++) v.A[i] = aggp[idx * E + i];
 #pragma unroll
-        for (int i = 0; i < D; i++) {
-          T acc = ld_payload(aggp + m * E + D * D + i);
+          for (int i = 0; i < D; i++) v.b[i] = aggp[idx * E + D * D + i];
+        } else {
+          aff_identity(v);
+        }
+        // ordered reduction: lane 0 (newest) o lane 1 o ... o lane 63 (oldest)
 #pragma unroll
-          for (int k = 0; k < D; k++) acc += ld_payload(aggp + m * E + i * D + k) * z[k];
-          t[i] = acc;
+        for (int off = 1; off < PINT_WAVE; off <<= 1) {
+          Aff<T, D> o;
+#pragma unroll
+          for (int i = 0; i < D * D; i++) o.A[i] = __shfl_down(v.A[i], off, PINT_WAVE);
+#pragma unroll
+          for (int i = 0; i < D; i++) o.b[i] = __shfl_down(v.b[i], off, PINT_WAVE);
+          if ((lane & (2 * off - 1)) == 0) aff_after(v, o);
         }
 #pragma unroll
-        for (int i = 0; i < D; i++) z[i] = t[i];
+        for (int i = 0; i < D * D; i++) v.A[i] = __shfl(v.A[i], 0, PINT_WAVE);
+#pragma unroll
+        for (int i = 0; i < D; i++) v.b[i] = __shfl(v.b[i], 0, PINT_WAVE);
+        aff_after(acc, v);
+        if (k < PINT_WAVE) {
+          const int64_t j = end - k;  // the inclusive predecessor
+          T zi[D];
+#pragma unroll
+          for (int i = 0; i < D; i++) zi[i] = j >= 0 ? inclp[j * D + i] : T(0);
+#pragma unroll
+          for (int i = 0; i < D; i++) {
+            T t = acc.b[i];
+#pragma unroll
+            for (int q = 0; q < D; q++) t += acc.A[i * D + q] * zi[q];
+            z[i] = t;
+          }
+          break;
+        }
+        end -= PINT_WAVE;
       }
     }
+    if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < D; i++) s_zin[i] = z[i];
-    // this tile's inclusive prefix: its aggregate applied to z_in
+      for (int i = 0; i < D; i++) s_zin[i] = z[i];
+      // this tile's inclusive prefix: its aggregate applied to z_in
 #pragma unroll
-    for (int i = 0; i < D; i++) {
-      T acc = s_tagg.b[i];
+      for (int i = 0; i < D; i++) {
+        T t = s_tagg.b[i];
 #pragma unroll
-      for (int k = 0; k < D; k++) acc += s_tagg.A[i * D + k] * z[k];
-      inclp[ts * D + i] = acc;
+        for (int q = 0; q < D; q++) t += s_tagg.A[i * D + q] * z[q];
+        inclp[ts * D + i] = t;
+      }
+      publish_flag(flags + ts, FLAG_INCL);
     }
-    publish_flag(flags + ts, FLAG_INCL);
   }
   __syncthreads();
 
@@ -301,8 +366,9 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
   if (tid == 0) s_tile = atomicAdd(a.counter, 1u);
   __syncthreads();
+  // sequences interleaved in tile order: early tiles of every sequence first
   const int64_t tile = s_tile;
-  const int64_t seq = tile / a.tiles_per_seq, ts = tile % a.tiles_per_seq;
+  const int64_t seq = tile % a.B, ts = tile / a.B;
   const int64_t e0 = ts * (int64_t)a.L;
   const int n_el = (int)((a.N - e0) < a.L ? (a.N - e0) : a.L);
   const T* Aseq = static_cast<const T*>(a.A) + (seq * a.N + e0) * D * D;
@@ -380,22 +446,28 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
     for (int idx = tid; idx < D * D; idx += NT) aggp[ts * E + idx] = sP[(idx / D) * PS + idx % D];
     for (int i = tid; i < D; i += NT) aggp[ts * E + D * D + i] = sq[i];
     __syncthreads();
-    if (tid == 0) {
-      publish_flag(flags + ts, FLAG_AGG);
-      int64_t j = ts - 1;
+    if (tid == 0) publish_flag(flags + ts, FLAG_AGG);
+    if (wv == 0) {
+      // nearest predecessor whose inclusive prefix is known
+      int64_t end = ts - 1;
       for (;;) {
-        const uint32_t f = wait_flag(flags + j, a.err);
-        if (f == FLAG_INCL || f == 0) break;
-        j--;
+        uint32_t f;
+        const int k = lookback_window(flags, end, a.err, f);
+        if (k < PINT_WAVE) {
+          end -= k;
+          break;
+        }
+        end -= PINT_WAVE;
       }
-      s_j = j;
+      if (lane == 0) s_j = end;
     }
     __syncthreads();
     const int64_t j = s_j;
-    for (int i = tid; i < D; i += NT) sz[i] = ld_payload(inclp + j * D + i);
+    for (int i = tid; i < D; i += NT) sz[i] = inclp[j * D + i];
     __syncthreads();
+    // the aggregates in between, oldest first, as matrix-vector products
     for (int64_t mm = j + 1; mm < ts; mm++)
-      block_matvec_g<T, D, NT>(aggp + mm * E, aggp + mm * E + D * D, sz, st, true);
+      block_matvec_g<T, D, NT>(aggp + mm * E, aggp + mm * E + D * D, sz, st, false);
   }
   // publish this tile's inclusive prefix: P z_in + q
   {
@@ -434,7 +506,20 @@ static int scan_tile_elems(int d, int dtype, int tile) {
     }
     return 0;
   }
-  return tile > 0 ? tile : 16;
+  if (tile > 0) return tile;
+  return 0;  // dense default: chosen from N, B and the CU count (dense_tile_len)
+}
+
+// Dense default tile length: enough tiles for one per compute unit, so the
+// chain of inclusive prefixes between tiles stays short.
+static int dense_tile_len(int64_t B, int64_t N) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t per_seq_tiles = (cus + B - 1) / B;
+  int64_t L = (N + per_seq_tiles - 1) / per_seq_tiles;
+  if (L < 1) L = 1;
+  if (L > (1 << 20)) L = 1 << 20;
+  return (int)L;
 }
 
 static bool scan_dense_d(int d) { return d == 16 || d == 32 || d == 40 || d == 64 || d == 128; }
@@ -442,7 +527,8 @@ static bool scan_dense_d(int d) { return d == 16 || d == 32 || d == 40 || d == 6
 size_t scan_ws_bytes(int d, int64_t B, int64_t N, int tile, int dtype) {
   if (d < 1 || B < 0 || N < 0) return 0;
   if (d > 8 && !scan_dense_d(d)) return 0;
-  const int L = scan_tile_elems(d, dtype, tile);
+  int L = scan_tile_elems(d, dtype, tile);
+  if (L <= 0 && d > 8) L = dense_tile_len(B, N);
   if (L <= 0) return 0;
   const int64_t tps = (N + L - 1) / L;
   const int64_t nt = B * tps;
@@ -477,7 +563,9 @@ int affine_scan(int d, int64_t B, int64_t N, int dtype, const void* A, const voi
   if (dtype != 0 && dtype != 1) return ST_INVALID;
   const size_t need = scan_ws_bytes(d, B, N, tile, dtype);
   if (!ws || ws_bytes < need) return ST_WORKSPACE;
-  const int L = scan_tile_elems(d, dtype, tile);
+  int L = scan_tile_elems(d, dtype, tile);
+  if (L <= 0 && d > 8) L = dense_tile_len(B, N);
+  if (L <= 0) return ST_INVALID;
   const int64_t tps = (N + L - 1) / L;
   const int64_t nt = B * tps;
   if (nt > 0x7fffffffLL) return ST_INVALID;
