@@ -77,6 +77,14 @@ __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* red) {
   return r;
 }
 
+// Workgroup barrier that orders LDS only: it waits for this wave's LDS
+// operations but leaves its outstanding global loads in flight, so register
+// prefetches survive it (__syncthreads waits for every memory operation).
+// Only for loops whose cross-wave communication is through LDS.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ------------------------------------------------------- affine elements --
 
 // An affine map z -> A z + b on R^D (A row-major).

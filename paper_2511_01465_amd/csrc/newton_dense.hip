@@ -61,21 +61,203 @@ __device__ __forceinline__ double wave_resid(const T* P, T dt, const T* X, const
   return wave_max(m);
 }
 
+// ------------------------------------------------- workgroup phases ------
+
+template <class S>
+struct DenseShape {
+  static constexpr int D = S::D, NT = S::NT, NW = NT / PINT_WAVE;
+  // recursion: QC adjacent threads per row, D*QC <= NT
+  static constexpr int QC = (D * 4 <= NT && D % 4 == 0) ? 4 : ((D * 2 <= NT && D % 2 == 0) ? 2 : 1);
+  static constexpr int JC = D / QC;
+  static_assert(D * QC <= NT, "row split");
+};
+
+// Shared-memory state of a dense solver workgroup.
+template <typename T, class S>
+struct DenseSmem {
+  typename S::Stage stage[S::SPP];
+  T P[S::NP], x0[S::D], z[2][S::D];
+  double red[S::NT / PINT_WAVE];
+  int64_t redi[S::NT / PINT_WAVE];
+  double wres[S::NT / PINT_WAVE];
+};
+
+// First step n >= p with ||h_n|| >= tol (or not finite): rounds of NW steps,
+// a wave per step.  Returns INT64_MAX if none; *hp receives ||h_fv||.
+template <typename T, class S>
+__device__ __forceinline__ int64_t dn_search(DenseSmem<T, S>& sm, T dt, const T* X, int64_t Tn, int64_t p, double tol,
+                             double* hp) {
+  constexpr int NT = S::NT, NW = NT / PINT_WAVE;
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  int64_t fv = INT64_MAX;
+  *hp = 0.0;
+  for (int64_t c0 = p; c0 <= Tn; c0 += NW) {
+    const int64_t n = c0 + wv;
+    int64_t v = INT64_MAX;
+    double hn = 0.0;
+    if (n <= Tn) {
+      hn = wave_resid<T, S>(sm.P, dt, X, sm.x0, n, lane);
+      if (!(hn < tol)) v = n;
+    }
+    if (lane == 0) sm.wres[wv] = hn;
+    fv = block_min_i64<NT>(v, sm.redi);
+    if (fv != INT64_MAX) {
+      *hp = sm.wres[fv - c0];
+      break;
+    }
+  }
+  return fv;
+}
+
+// max_n ||h_n|| over steps n = first, first + stride, ... <= Tn (a wave per step).
+template <typename T, class S>
+__device__ __forceinline__ double dn_resid_max(DenseSmem<T, S>& sm, T dt, const T* X, int64_t Tn, int64_t first,
+                               int64_t stride) {
+  constexpr int NT = S::NT, NW = NT / PINT_WAVE;
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  double r = 0.0;
+  for (int64_t n = first + wv * stride; n <= Tn; n += NW * stride)
+    r = fmax(r, wave_resid<T, S>(sm.P, dt, X, sm.x0, n, lane));
+  return block_max<NT>(r, sm.red);
+}
+
+// Elements of window steps m = m_first, m_first + m_stride, ... < len (in
+// groups of SPP): AT[m] = J(x_{lo+m-1}) transposed, bb[m] = Phi - x_{lo+m}.
+template <typename T, class S>
+__device__ __forceinline__ void dn_elements(DenseSmem<T, S>& sm, T dt, const T* X, int64_t lo, int64_t len,
+                            int64_t m_first, int64_t m_stride, T* AT, T* bb) {
+  constexpr int D = S::D, NT = S::NT, NW = NT / PINT_WAVE, SPP = S::SPP, JT = S::JT;
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  for (int64_t g0 = m_first; g0 < len; g0 += m_stride * SPP) {
+    for (int sl = wv; sl < SPP; sl += NW) {
+      const int64_t m = g0 + sl * m_stride;
+      if (m < len) {
+        const int64_t n = lo + m;
+        T xp[S::R], xc[S::R], phi[S::R];
+        wave_load<T, S>(X, sm.x0, n - 1, xp, lane);
+        wave_load<T, S>(X, sm.x0, n, xc, lane);
+        wave_rk4<T, S>(sm.P, dt, xp, phi, &sm.stage[sl], lane);
+#pragma unroll
+        for (int r = 0; r < S::R; r++) {
+          const int i = lane + 64 * r;
+          if (i < D) bb[m * D + i] = phi[r] - xc[r];
+        }
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < SPP * JT; t += NT) {
+      const int sl = t / JT, sub = t % JT;
+      const int64_t m = g0 + sl * m_stride;
+      if (m < len) S::jac_thread(&sm.stage[sl], sm.P, sub, dt, AT + m * D * D, 1, D);
+    }
+    __syncthreads();
+  }
+}
+
+// The window's Newton step, folded in order (eq. newton-step-recursion):
+// dx_0 = b_0, dx_m = J dx_{m-1} + b_m.  Writes the updated states
+// x_{lo+m} + dx_m to xnb and returns (block-uniform) the first window index
+// whose updated state is non-finite or beyond the guard (len if none; the
+// guard is not checked in plain mode).  The element rows, b and the old
+// states a thread needs are prefetched PD elements ahead into registers (a
+// ring with compile-time slots): they were written by other compute units.
+template <typename T, class S>
+__device__ __forceinline__ int64_t dn_fold(DenseSmem<T, S>& sm, const T* AT, const T* bb, const T* Xw,
+                                           T* xnb, int64_t len, bool plain, double guard) {
+  constexpr int D = S::D, NT = S::NT, QC = DenseShape<S>::QC, JC = DenseShape<S>::JC;
+  constexpr bool RING = JC <= 16;
+  constexpr int PD = RING ? (JC <= 10 ? 6 : 4) : 1;  // prefetch depth (elements)
+  const int tid = threadIdx.x;
+  const bool cth = tid < D * QC;
+  const int ri = tid / QC, rq = tid % QC;
+  int64_t bad_m = INT64_MAX;
+  T ring[PD][RING ? JC : 1], rb[PD], rx[PD];
+  if (cth)
+#pragma unroll
+    for (int u = 0; u < PD; u++) {
+      const int64_t m = u;
+      if (m < len) {
+        if constexpr (RING) {
+          if (m > 0)
+#pragma unroll
+            for (int jj = 0; jj < JC; jj++) ring[u][jj] = AT[m * D * D + (int64_t)(rq * JC + jj) * D + ri];
+        }
+        rb[u] = bb[m * D + ri];
+        rx[u] = Xw[m * D + ri];
+      }
+    }
+  int cur = 0;
+  for (int64_t m0 = 0; m0 < len; m0 += PD) {
+#pragma unroll
+    for (int u = 0; u < PD; u++) {
+      const int64_t m = m0 + u;
+      if (m < len) {
+        T part = T(0);
+        if (cth && m > 0) {
+          if constexpr (RING) {
+#pragma unroll
+            for (int jj = 0; jj < JC; jj++) part += ring[u][jj] * sm.z[cur][rq * JC + jj];
+          } else {
+            const T* Am = AT + m * D * D;
+#pragma unroll 16
+            for (int jj = 0; jj < JC; jj++) part += Am[(int64_t)(rq * JC + jj) * D + ri] * sm.z[cur][rq * JC + jj];
+          }
+        }
+        T bm = T(0), xm = T(0);
+        if (cth) {
+          bm = rb[u];
+          xm = rx[u];
+          const int64_t mn = m + PD;
+          if (mn < len) {
+            if constexpr (RING)
+#pragma unroll
+              for (int jj = 0; jj < JC; jj++) ring[u][jj] = AT[mn * D * D + (int64_t)(rq * JC + jj) * D + ri];
+            rb[u] = bb[mn * D + ri];
+            rx[u] = Xw[mn * D + ri];
+          }
+        }
+#pragma unroll
+        for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
+        if (cth && rq == 0) {
+          const T z = part + bm;
+          const T xn = xm + z;
+          sm.z[cur ^ 1][ri] = z;
+          xnb[m * D + ri] = xn;
+          if (!plain && bad_m == INT64_MAX && (!finite_(xn) || fabs((double)xn) > guard)) bad_m = m;
+        }
+        lds_barrier();
+        cur ^= 1;
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t q = block_min_i64<NT>(bad_m, sm.redi);
+  return q == INT64_MAX ? len : q;
+}
+
+// Write the accepted part [0, q) of the updated window states.
+template <typename T, class S>
+__device__ __forceinline__ void dn_commit(T* Xw, const T* xnb, int64_t q) {
+  for (int64_t idx = threadIdx.x; idx < q * S::D; idx += S::NT) Xw[idx] = xnb[idx];
+  __syncthreads();
+}
+
+template <typename T, class S>
+__device__ __forceinline__ void dn_load_inst(DenseSmem<T, S>& sm, const DenseKArgs& a, int64_t inst) {
+  const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
+  for (int i = threadIdx.x; i < S::NP; i += S::NT) sm.P[i] = Pg[i];
+  const T* xg = static_cast<const T*>(a.x0) + inst * S::D;
+  for (int i = threadIdx.x; i < S::D; i += S::NT) sm.x0[i] = xg[i];
+  __syncthreads();
+}
+
+// One workgroup per instance (device work queue), whole Newton loop.
 template <typename T, class S>
 __global__ __launch_bounds__(S::NT) void k_newton_dense(DenseKArgs a) {
-  constexpr int D = S::D, NP = S::NP, NT = S::NT, NW = NT / PINT_WAVE;
-  constexpr int SPP = S::SPP, JT = S::JT;
-  // recursion: QC adjacent threads per row, D*QC <= NT
-  constexpr int QC = (D * 4 <= NT && D % 4 == 0) ? 4 : ((D * 2 <= NT && D % 2 == 0) ? 2 : 1);
-  constexpr int JC = D / QC;
-  static_assert(D * QC <= NT, "row split");
-  __shared__ typename S::Stage s_stage[SPP];
-  __shared__ T s_P[NP], s_x0[D], s_z[2][D];
-  __shared__ double s_red[NW];
-  __shared__ int64_t s_redi[NW];
-  __shared__ double s_wres[NW];
+  constexpr int D = S::D, NT = S::NT;
+  __shared__ DenseSmem<T, S> sm;
   __shared__ uint32_t s_slot;
-  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  const int tid = threadIdx.x;
   const T dt = (T)a.dt;
   T* slot = static_cast<T*>(a.ws_elems) + (int64_t)blockIdx.x * a.slot_stride;
   T* AT = slot;
@@ -90,15 +272,9 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense(DenseKArgs a) {
     if (inst >= a.B) break;
     const int64_t Tn = a.T_uniform;
     T* X = static_cast<T*>(a.traj) + inst * Tn * D;
-    {
-      const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
-      for (int i = tid; i < NP; i += NT) s_P[i] = Pg[i];
-      const T* xg = static_cast<const T*>(a.x0) + inst * D;
-      for (int i = tid; i < D; i += NT) s_x0[i] = xg[i];
-    }
-    __syncthreads();
+    dn_load_inst<T, S>(sm, a, inst);
     if (a.guess == 0)
-      for (int64_t idx = tid; idx < Tn * D; idx += NT) X[idx] = s_x0[idx % D];
+      for (int64_t idx = tid; idx < Tn * D; idx += NT) X[idx] = sm.x0[idx % D];
     __syncthreads();
 
     const bool plain = (a.window <= 0);
@@ -108,32 +284,15 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense(DenseKArgs a) {
     while (Tn > 0) {
       int64_t lo, hi;
       if (plain) {
-        double r = 0.0;
-        for (int64_t n = 1 + wv; n <= Tn; n += NW) r = fmax(r, wave_resid<T, S>(s_P, dt, X, s_x0, n, lane));
-        r = block_max<NT>(r, s_red);
+        const double r = dn_resid_max<T, S>(sm, dt, X, Tn, 1, 1);
         if (!(r < INFINITY)) { st = ST_NONFINITE; break; }
         if (r < a.tol) { st = ST_OK; break; }
         if (k >= a.max_iter) { st = ST_NOT_CONVERGED; break; }
         lo = 1;
         hi = Tn;
       } else {
-        int64_t fv = INT64_MAX;
-        double hp = 0.0;
-        for (int64_t c0 = p; c0 <= Tn; c0 += NW) {
-          const int64_t n = c0 + wv;
-          int64_t v = INT64_MAX;
-          double hn = 0.0;
-          if (n <= Tn) {
-            hn = wave_resid<T, S>(s_P, dt, X, s_x0, n, lane);
-            if (!(hn < a.tol)) v = n;
-          }
-          if (lane == 0) s_wres[wv] = hn;
-          fv = block_min_i64<NT>(v, s_redi);
-          if (fv != INT64_MAX) {
-            hp = s_wres[fv - c0];
-            break;
-          }
-        }
+        double hp;
+        const int64_t fv = dn_search<T, S>(sm, dt, X, Tn, p, a.tol, &hp);
         if (fv == INT64_MAX) { st = ST_OK; break; }
         p = fv;
         if (!(hp < INFINITY)) { st = ST_NONFINITE; break; }
@@ -142,108 +301,157 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense(DenseKArgs a) {
         hi = (W >= Tn - p + 1) ? Tn : p + W - 1;
       }
       const int64_t len = hi - lo + 1;
-
-      // Elements of the window: e_m = (J(x_{lo+m-1}), Phi(x_{lo+m-1}) - x_{lo+m}).
-      for (int64_t m0 = 0; m0 < len; m0 += SPP) {
-        for (int sl = wv; sl < SPP; sl += NW) {
-          const int64_t m = m0 + sl;
-          if (m < len) {
-            const int64_t n = lo + m;
-            T xp[S::R], xc[S::R], phi[S::R];
-            wave_load<T, S>(X, s_x0, n - 1, xp, lane);
-            wave_load<T, S>(X, s_x0, n, xc, lane);
-            wave_rk4<T, S>(s_P, dt, xp, phi, &s_stage[sl], lane);
-#pragma unroll
-            for (int r = 0; r < S::R; r++) {
-              const int i = lane + 64 * r;
-              if (i < D) bb[m * D + i] = phi[r] - xc[r];
-            }
-          }
-        }
-        __syncthreads();
-        for (int t = tid; t < SPP * JT; t += NT) {
-          const int sl = t / JT, sub = t % JT;
-          const int64_t m = m0 + sl;
-          if (m < len) S::jac_thread(&s_stage[sl], s_P, sub, dt, AT + m * D * D, 1, D);
-        }
-        __syncthreads();
-      }
-
-      // Newton step over the window: dx_{lo} = b_0, dx_{lo+m} = J dx + b_m.
-      {
-        const bool cth = tid < D * QC;
-        const int ri = tid / QC, rq = tid % QC;
-        if (tid < D) s_z[0][tid] = T(0);
-        __syncthreads();
-        // rows of the next element are prefetched into registers when they
-        // fit (JC <= 16); otherwise read in the dot loop
-        constexpr bool PF = JC <= 16;
-        T an[PF ? JC : 1];
-        if (PF && cth && len > 1)
-#pragma unroll
-          for (int jj = 0; jj < (PF ? JC : 1); jj++) an[jj] = AT[(int64_t)D * D + (int64_t)(rq * JC + jj) * D + ri];
-        int cur = 0;
-        for (int64_t m = 0; m < len; m++) {
-          T part = T(0);
-          if (cth && m > 0) {
-            if constexpr (PF) {
-#pragma unroll
-              for (int jj = 0; jj < JC; jj++) part += an[jj] * s_z[cur][rq * JC + jj];
-              if (m + 1 < len) {
-                const T* An = AT + (m + 1) * D * D;
-#pragma unroll
-                for (int jj = 0; jj < JC; jj++) an[jj] = An[(int64_t)(rq * JC + jj) * D + ri];
-              }
-            } else {
-              const T* Am = AT + m * D * D;
-#pragma unroll 16
-              for (int jj = 0; jj < JC; jj++) part += Am[(int64_t)(rq * JC + jj) * D + ri] * s_z[cur][rq * JC + jj];
-            }
-          }
-#pragma unroll
-          for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
-          if (cth && rq == 0) {
-            const T z = part + bb[m * D + ri];
-            s_z[cur ^ 1][ri] = z;
-            dxb[m * D + ri] = z;
-          }
-          __syncthreads();
-          cur ^= 1;
-        }
-      }
-
-      // Accept below the first non-finite / out-of-guard updated state.
-      int64_t q = INT64_MAX;
-      if (!plain) {
-        int64_t v = INT64_MAX;
-        for (int64_t m = tid; m < len; m += NT) {
-          bool bad = false;
-          for (int i = 0; i < D; i++) {
-            const T xn = X[(lo + m - 1) * D + i] + dxb[m * D + i];
-            bad = bad || !finite_(xn) || fabs((double)xn) > a.guard;
-          }
-          if (bad) { v = lo + m; break; }
-        }
-        q = block_min_i64<NT>(v, s_redi);
-      }
-      for (int64_t idx = tid; idx < len * D; idx += NT) {
-        const int64_t m = idx / D;
-        if (lo + m < q) X[(lo - 1) * D + idx] += dxb[idx];
-      }
-      __syncthreads();
-      if (q == lo) { st = ST_NONFINITE; break; }
+      dn_elements<T, S>(sm, dt, X, lo, len, 0, 1, AT, bb);
+      const int64_t q = dn_fold<T, S>(sm, AT, bb, X + (lo - 1) * D, dxb, len, plain, a.guard);
+      dn_commit<T, S>(X + (lo - 1) * D, dxb, q);
+      if (q == 0) { st = ST_NONFINITE; break; }
       k++;
     }
     __syncthreads();
-    double r = 0.0;
-    for (int64_t n = 1 + wv; n <= Tn; n += NW) r = fmax(r, wave_resid<T, S>(s_P, dt, X, s_x0, n, lane));
-    r = block_max<NT>(r, s_red);
+    const double r = dn_resid_max<T, S>(sm, dt, X, Tn, 1, 1);
     if (tid == 0) {
       a.iters[inst] = k;
       a.resid[inst] = r;
       a.status[inst] = st;
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------- cooperative variant -----
+
+// Per-instance control block of the cooperative solver (64 bytes).
+struct CoopCtl {
+  uint32_t bar_count, bar_gen;
+  int64_t lo, hi;     // window decided by workgroup 0
+  int32_t done, st;
+  int64_t k;
+  unsigned long long rmax;  // final residual (bits of a non-negative double)
+  uint32_t err, pad0;
+  int64_t pad1;
+};
+static_assert(sizeof(CoopCtl) == 64, "control block size");
+
+// Barrier among the G workgroups of one instance.  Release fence before
+// arriving, acquire fence after leaving; the wait is bounded.
+__device__ __forceinline__ void coop_barrier(CoopCtl* c, int G, uint32_t& gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t target = gen + 1;
+    const uint32_t prev = atomicAdd(&c->bar_count, 1u);
+    if (prev == (uint32_t)(G - 1)) {
+      __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      __hip_atomic_store(&c->bar_gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      for (uint64_t it = 0;
+           __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target; it++) {
+        if (it > (1ull << 28)) {
+          atomicOr(&c->err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __threadfence();
+    gen = target;
+  }
+  __syncthreads();
+}
+
+// G workgroups per instance (windowed mode): all of them build the
+// window's elements; workgroup 0 folds the recursion, applies the guarded
+// update and searches the next window.  Two barriers per update.  Needs all
+// workgroups resident at once (cooperative launch).
+template <typename T, class S>
+__global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G, CoopCtl* ctl) {
+  constexpr int D = S::D, NT = S::NT;
+  __shared__ DenseSmem<T, S> sm;
+  __shared__ int64_t s_win[2];
+  __shared__ int32_t s_done;
+  const int tid = threadIdx.x;
+  const int64_t inst = blockIdx.x / G;
+  const int g = blockIdx.x % G;
+  const T dt = (T)a.dt;
+  CoopCtl* c = ctl + inst;
+  T* slot = static_cast<T*>(a.ws_elems) + inst * a.slot_stride;
+  T* AT = slot;
+  T* bb = AT + a.Wt * D * D;
+  T* dxb = bb + a.Wt * D;
+  const int64_t Tn = a.T_uniform;
+  T* X = static_cast<T*>(a.traj) + inst * Tn * D;
+  const int64_t W = a.window;
+  uint32_t gen = 0;
+
+  dn_load_inst<T, S>(sm, a, inst);
+  if (a.guess == 0)
+    for (int64_t idx = (int64_t)g * NT + tid; idx < Tn * D; idx += (int64_t)G * NT) X[idx] = sm.x0[idx % D];
+
+  // workgroup 0 owns the iteration state
+  int64_t k = 0;
+  int st = ST_OK;
+  auto decide = [&](int64_t p) {  // search from p, publish the next window
+    double hp;
+    int64_t lo = 0, hi = 0;
+    int done = 0;
+    const int64_t fv = Tn > 0 ? dn_search<T, S>(sm, dt, X, Tn, p, a.tol, &hp) : INT64_MAX;
+    if (fv == INT64_MAX) {
+      st = ST_OK;
+      done = 1;
+    } else if (!(hp < INFINITY)) {
+      st = ST_NONFINITE;
+      done = 1;
+    } else if (k >= a.max_iter) {
+      st = ST_NOT_CONVERGED;
+      done = 1;
+    } else {
+      lo = fv;
+      hi = (W >= Tn - fv + 1) ? Tn : fv + W - 1;
+    }
+    if (tid == 0) {
+      c->lo = lo;
+      c->hi = hi;
+      c->done = done;
+    }
+  };
+
+  coop_barrier(c, G, gen);  // initial iterate written everywhere
+  if (g == 0) decide(1);
+  coop_barrier(c, G, gen);
+  for (;;) {
+    if (tid == 0) {
+      s_win[0] = c->lo;
+      s_win[1] = c->hi;
+      s_done = c->done;
+    }
+    __syncthreads();
+    if (s_done) break;
+    const int64_t lo = s_win[0], len = s_win[1] - s_win[0] + 1;
+    dn_elements<T, S>(sm, dt, X, lo, len, g, G, AT, bb);
+    coop_barrier(c, G, gen);
+    if (g == 0) {
+      const int64_t q = dn_fold<T, S>(sm, AT, bb, X + (lo - 1) * D, dxb, len, false, a.guard);
+      dn_commit<T, S>(X + (lo - 1) * D, dxb, q);
+      if (q == 0) {
+        st = ST_NONFINITE;
+        if (tid == 0) c->done = 1;
+      } else {
+        k++;
+        decide(lo);
+      }
+    }
+    coop_barrier(c, G, gen);
+  }
+  // final residual: steps split over the G workgroups
+  const double r = dn_resid_max<T, S>(sm, dt, X, Tn, 1 + g, G);
+  if (tid == 0) atomic_max_nonneg(reinterpret_cast<double*>(&c->rmax), r);
+  coop_barrier(c, G, gen);
+  if (g == 0 && tid == 0) {
+    a.iters[inst] = k;
+    a.resid[inst] = __longlong_as_double((long long)__hip_atomic_load(&c->rmax, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_AGENT));
+    a.status[inst] = c->err ? ST_DEVICE : st;
   }
 }
 
@@ -403,8 +611,7 @@ static int num_cus() {
   return cus;
 }
 
-// Workgroups for the persistent dense solver: one per instance, at most one
-// per compute unit.
+// Workgroups for the one-workgroup-per-instance solver: at most one per CU.
 static int dense_grid(int64_t B) {
   const int64_t cu = num_cus();
   return (int)(B < cu ? B : cu);
@@ -415,31 +622,77 @@ static int64_t dense_Wt(const SolveArgs& a) {
   return (a.window <= 0 || a.window >= T) ? T : a.window;
 }
 
+// Workgroups per instance for the cooperative solver (windowed mode only):
+// enough for one Jacobian pass per workgroup over the window, all of them
+// resident at once; 1 means "use the one-workgroup solver".
+template <typename T, class S>
+static int coop_groups(const SolveArgs& a) {
+  if (a.window <= 0 || a.B <= 0 || a.T_uniform <= 0) return 1;
+  const int64_t W = dense_Wt(a);
+  int64_t G = (W + S::SPP - 1) / S::SPP;
+  if (G > 64) G = 64;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_newton_dense_coop<T, S>, S::NT, 0) != hipSuccess)
+    return 1;
+  const int64_t cap = (int64_t)per_cu * num_cus();
+  while (G > 1 && a.B * G > cap) G--;
+  return G >= 2 ? (int)G : 1;
+}
+
+struct DenseWs {
+  size_t ctl_off, slots_off, per_slot, total;
+  int64_t nslots;
+};
+
+template <typename T, class S>
+static DenseWs dense_ws_layout(const SolveArgs& a) {
+  DenseWs l{};
+  const int64_t Wt = dense_Wt(a) > 0 ? dense_Wt(a) : 1;
+  const int64_t B = a.B > 0 ? a.B : 1;
+  l.per_slot = align_up((size_t)slot_scalars<S>(Wt) * sizeof(T));
+  l.nslots = B > dense_grid(B) ? B : dense_grid(B);
+  l.ctl_off = 256;
+  l.slots_off = l.ctl_off + align_up((size_t)B * sizeof(CoopCtl));
+  l.total = l.slots_off + l.per_slot * (size_t)l.nslots;
+  return l;
+}
+
 size_t dense_ws_bytes(const SolveArgs& a) {
-  size_t per = 0;
+  size_t total = 0;
   dispatch_dense(a.dtype, a.system, a.d, [&](auto t, auto s) {
     using T = decltype(t);
     using S = decltype(s);
-    per = (size_t)slot_scalars<S>(dense_Wt(a) > 0 ? dense_Wt(a) : 1) * sizeof(T);
+    total = dense_ws_layout<T, S>(a).total;
     return ST_OK;
   });
-  return 256 + align_up(per) * (size_t)(dense_grid(a.B > 0 ? a.B : 1));
+  return total;
 }
 
 int dense_solve(const SolveArgs& a) {
   if (!a.ws || a.ws_bytes < dense_ws_bytes(a)) return ST_WORKSPACE;
-  DenseKArgs k = to_dk(a);
-  k.queue = static_cast<uint32_t*>(a.ws);
-  k.ws_elems = static_cast<char*>(a.ws) + 256;
-  k.Wt = dense_Wt(a);
-  if (int rc = fill_u32(k.queue, 1, 0u, a.stream)) return rc;
-  const int grid = dense_grid(a.B);
-  return dispatch_dense(a.dtype, a.system, a.d, [&](auto t, auto s) {
+  return dispatch_dense(a.dtype, a.system, a.d, [&](auto t, auto s) -> int {
     using T = decltype(t);
     using S = decltype(s);
-    k.slot_stride = (int64_t)(align_up((size_t)slot_scalars<S>(k.Wt > 0 ? k.Wt : 1) * sizeof(T)) /
-                              sizeof(T));
-    hipLaunchKernelGGL((k_newton_dense<T, S>), dim3(grid), dim3(S::NT), 0, a.stream, k);
+    const DenseWs l = dense_ws_layout<T, S>(a);
+    char* w = static_cast<char*>(a.ws);
+    DenseKArgs k = to_dk(a);
+    k.queue = reinterpret_cast<uint32_t*>(w);
+    k.ws_elems = w + l.slots_off;
+    k.Wt = dense_Wt(a);
+    k.slot_stride = (int64_t)(l.per_slot / sizeof(T));
+    CoopCtl* ctl = reinterpret_cast<CoopCtl*>(w + l.ctl_off);
+    // queue counter and control blocks start at zero (a kernel, not a memset)
+    if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w), l.slots_off / 4, 0u, a.stream)) return rc;
+    const int G = coop_groups<T, S>(a);
+    if (G >= 2) {
+      int Gv = G;
+      void* args[] = {&k, &Gv, &ctl};
+      const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_newton_dense_coop<T, S>),
+                                                      dim3((unsigned)(a.B * G)), dim3(S::NT), args, 0, a.stream);
+      if (e == hipSuccess) return ST_OK;
+      (void)hipGetLastError();  // fall back to one workgroup per instance
+    }
+    hipLaunchKernelGGL((k_newton_dense<T, S>), dim3(dense_grid(a.B)), dim3(S::NT), 0, a.stream, k);
     return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
   });
 }

@@ -164,3 +164,18 @@ def test_fp32_dense(pint, orc, kind):
     assert np.abs(h).max() <= (2e-5 if kind == "l96" else 1e-5) + 16 * np.finfo(np.float32).eps * scale
     ref = orc.integrate(w.system, P64, w.dt, 50, x064)
     assert np.abs(got[:50] - ref).max() <= 1e-4 * scale
+
+
+def test_lorenz96_large_batch_one_workgroup_path(pint, orc):
+    """300 instances exceed the co-resident capacity for several workgroups
+    per instance, so this runs the one-workgroup-per-instance solver."""
+    w = W.lorenz96(T=48, B=300, window=16)
+    traj, iters, resid, status = pint.solve(pint.LORENZ96, _t(w.x0), _t(w.params), w.dt, 48,
+                                            tol=1e-12, window=16)
+    torch.cuda.synchronize()
+    traj = traj.cpu().numpy()
+    for b in (0, 1, 150, 299):
+        ref = orc.newton(w.system, w.params[b], w.dt, 48, w.x0[b], tol=1e-12, window=16, max_iter=200)
+        assert int(status[b]) == ref["status"] == 0
+        assert int(iters[b]) == ref["iters"]
+        assert np.abs(traj[b] - ref["traj"]).max() <= 1e-10
