@@ -59,18 +59,23 @@ def _time(fn, reps, stream):
 
 def leg_scan_small(P, torch, dev, stream, reps=5):
     """Small-d affine scan alone on 2^24 orthogonal elements per d (HBM bound):
-    algorithmic bytes per element (d^2 + d) * 8 read + d * 8 written."""
+    algorithmic bytes per element (d^2 + d) * 8 read + d * 8 written.  A seeded
+    block of 2^20 random rotations is repeated 16 times (products stay
+    orthogonal, so the scan stays bounded)."""
     import workloads as W
     out = {}
     N = 1 << 24
-    for d in (2, 3, 4):
+    for d in (2, 3, 4, 8):
         A = torch.empty((1, N, d, d), dtype=torch.float64, device=dev)
         b = torch.empty((1, N, d), dtype=torch.float64, device=dev)
+        # one seeded block of 2^20 rotations, repeated over the stream
         chunk = 1 << 20
+        Ah, bh = W.random_affine(chunk, d, seed=d, kind="rotation")
+        Ad, bd = torch.from_numpy(Ah).to(dev), torch.from_numpy(bh).to(dev)
         for c0 in range(0, N, chunk):
-            Ah, bh = W.random_affine(chunk, d, seed=c0 // chunk, kind="rotation")
-            A[0, c0:c0 + chunk] = torch.from_numpy(Ah)
-            b[0, c0:c0 + chunk] = torch.from_numpy(bh)
+            A[0, c0:c0 + chunk] = Ad
+            b[0, c0:c0 + chunk] = bd
+        del Ad, bd
         z = torch.empty((1, N, d), dtype=torch.float64, device=dev)
         ws = torch.empty(P.pint_scan_workspace_bytes(d, 1, N, 0, P.F64), dtype=torch.uint8, device=dev)
         ms = _time(lambda: P.pint_affine_scan(d, 1, N, P.F64, A, b, None, z, 0, ws, stream), reps, stream)

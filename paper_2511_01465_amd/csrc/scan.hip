@@ -8,9 +8,17 @@
 // descriptors until it finds one whose inclusive prefix is known.  Because
 // the prefix starts from a known z_0, an inclusive prefix is just the vector
 // z at the tile's end, and stepping back over an aggregate-only predecessor
-// costs a matrix-vector product, not a matrix product.  Descriptors are
-// published payload first, then a device-scope fence, then the flag; waits
-// are bounded so every wave exits even if a predecessor never publishes.
+// costs a matrix-vector product, not a matrix product.
+//
+// Descriptor protocol.  The payload (aggregate map, inclusive vector) is
+// written and read with device-scope atomic accesses, which are coherent
+// across the chip's L2 slices on their own; the writer waits for its payload
+// stores to complete (vmcnt) before it stores the flag, and a reader issues
+// its payload loads only after it has seen the flag.  A generic device-scope
+// fence would write back and invalidate the whole L2 of the writer's and the
+// reader's die on every publish and every wait, which serialises the tiles.
+// Waits are bounded so every wave exits even if a predecessor never
+// publishes.
 //
 //   small d (<= 8): tiles staged through LDS, each thread folds a run of
 //     elements, wave shuffles + LDS scan the thread aggregates;
@@ -38,29 +46,23 @@ struct ScanArgs {
 constexpr uint32_t FLAG_AGG = 1, FLAG_INCL = 2;
 constexpr uint64_t SPIN_LIMIT = 1ull << 24;
 
+template <typename T>
+__device__ __forceinline__ void st_payload(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_payload(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by the thread that stored the payload (or after a workgroup barrier,
+// which itself waits for every wave's stores): the payload stores complete
+// before the flag store is issued.
 __device__ __forceinline__ void publish_flag(uint32_t* f, uint32_t v) {
-  __threadfence();
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-// Wait until the flag is non-zero (bounded); returns it (0 on timeout, after
-// raising the error word).  The fence after a non-zero flag orders the
-// payload reads after it.
-__device__ __forceinline__ uint32_t wait_flag(const uint32_t* f, uint32_t* err) {
-  for (uint64_t it = 0;; it++) {
-    const uint32_t v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (v) {
-      __threadfence();
-      return v;
-    }
-    if (it > SPIN_LIMIT) {
-      atomicOr(err, 1u);
-      return 0;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-}
-
 
 // Wave-parallel lookback search (all 64 lanes of one wave call it): lanes
 // read the flags of predecessors end, end-1, ..., end-63 at once.  Returns,
@@ -68,6 +70,7 @@ __device__ __forceinline__ uint32_t wait_flag(const uint32_t* f, uint32_t* err) 
 // the first inclusive one within the window (k = 64: none inclusive yet, all
 // 64 aggregates), after waiting until no predecessor in front of the first
 // inclusive one is still unpublished.  `f_out` receives this lane's flag.
+// Payload reads after the return must use ld_payload.
 __device__ __forceinline__ int lookback_window(const uint32_t* flags, int64_t end, uint32_t* err,
                                                uint32_t& f_out) {
   const int lane = threadIdx.x % PINT_WAVE;
@@ -80,7 +83,6 @@ __device__ __forceinline__ int lookback_window(const uint32_t* flags, int64_t en
     const int first = incl ? __ffsll((long long)incl) - 1 : PINT_WAVE;
     const uint64_t before = first >= PINT_WAVE ? ~0ull : ((1ull << first) - 1);
     if (!(zero & before)) {
-      __threadfence();  // acquire: payload reads below see the publishers' data
       f_out = f;
       return first;
     }
@@ -93,28 +95,101 @@ __device__ __forceinline__ int lookback_window(const uint32_t* flags, int64_t en
   }
 }
 
-template <typename T>
-__device__ __forceinline__ T ld_payload(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // ----------------------------------------------------------- small d ------
 
-template <int D, typename T>
-constexpr int small_nt() { return D <= 4 ? 256 : 64; }
+// Widest load/store unit (in scalars, 16 or 8 bytes, else 1) that divides a
+// per-thread run of `run` scalars.
+template <typename T>
+constexpr int vec_width(int run) {
+  return (run * (int)sizeof(T)) % 16 == 0 ? 16 / (int)sizeof(T)
+         : (run * (int)sizeof(T)) % 8 == 0 ? 8 / (int)sizeof(T) : 1;
+}
 
+// Tile shape of the small-d scan: NT threads, S consecutive elements per
+// thread, the tile staged in LDS within a 48 KiB budget (three workgroups
+// per compute unit).  RA / RB: scalars of A / b per thread run.
 template <int D, typename T>
-constexpr int small_s() {
-  constexpr int bytes = (D * D + D) * (int)sizeof(T) * small_nt<D, T>();
-  constexpr int s = 49152 / bytes;
-  return s < 1 ? 1 : (s > 16 ? 16 : s);
+struct SmallShape {
+  static constexpr int NT = D <= 4 ? 256 : 64;
+  static constexpr int E = D * D + D;
+  static constexpr int S0 = 49152 / (E * (int)sizeof(T) * NT);
+  static constexpr int S = S0 < 1 ? 1 : (S0 > 16 ? 16 : S0);
+  static constexpr int TILE = NT * S;
+  static constexpr int RA = S * D * D, RB = S * D;
+  static constexpr int VA = vec_width<T>(RA), VB = vec_width<T>(RB);
+};
+
+// Global -> LDS copy of n <= NT*RUN scalars into the blocked layout in which
+// thread t's run of RUN scalars starts at t*(RUN+1) (one pad scalar per run,
+// so the runs read back at an odd stride hit distinct LDS banks).  Global
+// reads are striped over the block, so each wave instruction reads one
+// contiguous span, and all are issued before the first LDS write; vectors of
+// V scalars when the tile is full and g is aligned.
+template <typename T, int RUN, int V, int NT>
+__device__ __forceinline__ void stage_in(const T* __restrict__ g, T* lds, int n, int tid) {
+  if constexpr (V > 1) {
+    if (n == NT * RUN && (reinterpret_cast<uintptr_t>(g) % (V * sizeof(T))) == 0) {
+      typedef T vec_t __attribute__((ext_vector_type(V)));
+      constexpr int NV = RUN / V;
+      vec_t r[NV];
+#pragma unroll
+      for (int j = 0; j < NV; j++) r[j] = reinterpret_cast<const vec_t*>(g)[j * NT + tid];
+#pragma unroll
+      for (int j = 0; j < NV; j++) {
+        const int q = (j * NT + tid) * V;
+        const int p = q + q / RUN;
+#pragma unroll
+        for (int c = 0; c < V; c++) lds[p + c] = r[j][c];
+      }
+      return;
+    }
+  }
+  T r[RUN];
+#pragma unroll
+  for (int j = 0; j < RUN; j++) {
+    const int q = j * NT + tid;
+    r[j] = q < n ? g[q] : T(0);
+  }
+#pragma unroll
+  for (int j = 0; j < RUN; j++) {
+    const int q = j * NT + tid;
+    if (q < n) lds[q + q / RUN] = r[j];
+  }
+}
+
+// LDS (blocked, padded as in stage_in) -> global, striped over the block.
+template <typename T, int RUN, int V, int NT>
+__device__ __forceinline__ void stage_out(T* __restrict__ g, const T* lds, int n, int tid) {
+  if constexpr (V > 1) {
+    if (n == NT * RUN && (reinterpret_cast<uintptr_t>(g) % (V * sizeof(T))) == 0) {
+      typedef T vec_t __attribute__((ext_vector_type(V)));
+      constexpr int NV = RUN / V;
+#pragma unroll
+      for (int j = 0; j < NV; j++) {
+        const int q = (j * NT + tid) * V;
+        const int p = q + q / RUN;
+        vec_t v;
+#pragma unroll
+        for (int c = 0; c < V; c++) v[c] = lds[p + c];
+        reinterpret_cast<vec_t*>(g)[j * NT + tid] = v;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RUN; j++) {
+    const int q = j * NT + tid;
+    if (q < n) g[q] = lds[q + q / RUN];
+  }
 }
 
 template <typename T, int D>
-__global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
-  constexpr int NT = small_nt<D, T>(), S = small_s<D, T>(), TILE = NT * S, NW = NT / PINT_WAVE;
-  constexpr int E = D * D + D;
-  __shared__ T s_el[TILE * E];
+__global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs a) {
+  using SH = SmallShape<D, T>;
+  constexpr int NT = SH::NT, S = SH::S, TILE = SH::TILE, NW = NT / PINT_WAVE, E = SH::E;
+  constexpr int RA = SH::RA, RB = SH::RB, PA = RA + 1, PB = RB + 1;
+  __shared__ T sA[NT * PA];
+  __shared__ T sb[NT * PB];
   __shared__ Aff<T, D> s_aff[NW];
   __shared__ Aff<T, D> s_tagg;
   __shared__ T s_zin[D], s_wz[NW][D];
@@ -128,24 +203,23 @@ __global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
   const int n_el = (int)((a.N - e0) < TILE ? (a.N - e0) : TILE);
   const T* Ag = static_cast<const T*>(a.A) + (seq * a.N + e0) * D * D;
   const T* bg = static_cast<const T*>(a.b) + (seq * a.N + e0) * D;
-  T* sA = s_el;
-  T* sb = s_el + TILE * D * D;
-  for (int i = tid; i < n_el * D * D; i += NT) sA[i] = Ag[i];
-  for (int i = tid; i < n_el * D; i += NT) sb[i] = bg[i];
+  stage_in<T, RA, SH::VA, NT>(Ag, sA, n_el * D * D, tid);
+  stage_in<T, RB, SH::VB, NT>(bg, sb, n_el * D, tid);
   __syncthreads();
 
   // each thread folds its S consecutive elements into one map
+  const T* myA = sA + tid * PA;
+  const T* myb = sb + tid * PB;
   Aff<T, D> agg;
   aff_identity(agg);
 #pragma unroll
   for (int s = 0; s < S; s++) {
-    const int idx = tid * S + s;
-    if (idx < n_el) {
+    if (tid * S + s < n_el) {
       Aff<T, D> e;
 #pragma unroll
-      for (int i = 0; i < D * D; i++) e.A[i] = sA[idx * D * D + i];
+      for (int i = 0; i < D * D; i++) e.A[i] = myA[s * D * D + i];
 #pragma unroll
-      for (int i = 0; i < D; i++) e.b[i] = sb[idx * D + i];
+      for (int i = 0; i < D; i++) e.b[i] = myb[s * D + i];
       aff_after(e, agg);
       agg = e;
     }
@@ -167,9 +241,9 @@ __global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
     } else {
       if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < D * D; i++) aggp[ts * E + i] = s_tagg.A[i];
+        for (int i = 0; i < D * D; i++) st_payload(aggp + ts * E + i, s_tagg.A[i]);
 #pragma unroll
-        for (int i = 0; i < D; i++) aggp[ts * E + D * D + i] = s_tagg.b[i];
+        for (int i = 0; i < D; i++) st_payload(aggp + ts * E + D * D + i, s_tagg.b[i]);
         publish_flag(flags + ts, FLAG_AGG);
       }
       // acc = composition of the aggregates passed so far (newest applied last)
@@ -184,9 +258,9 @@ __global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
         const int64_t idx = end - lane;
         if (lane < k) {
 #pragma unroll
-          for (int i = 0; i < D * D; i++) v.A[i] = aggp[idx * E + i];
+          for (int i = 0; i < D * D; i++) v.A[i] = ld_payload(aggp + idx * E + i);
 #pragma unroll
-          for (int i = 0; i < D; i++) v.b[i] = aggp[idx * E + D * D + i];
+          for (int i = 0; i < D; i++) v.b[i] = ld_payload(aggp + idx * E + D * D + i);
         } else {
           aff_identity(v);
         }
@@ -209,7 +283,7 @@ __global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
           const int64_t j = end - k;  // the inclusive predecessor
           T zi[D];
 #pragma unroll
-          for (int i = 0; i < D; i++) zi[i] = j >= 0 ? inclp[j * D + i] : T(0);
+          for (int i = 0; i < D; i++) zi[i] = j >= 0 ? ld_payload(inclp + j * D + i) : T(0);
 #pragma unroll
           for (int i = 0; i < D; i++) {
             T t = acc.b[i];
@@ -231,7 +305,7 @@ __global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
         T t = s_tagg.b[i];
 #pragma unroll
         for (int q = 0; q < D; q++) t += s_tagg.A[i * D + q] * z[q];
-        inclp[ts * D + i] = t;
+        st_payload(inclp + ts * D + i, t);
       }
       publish_flag(flags + ts, FLAG_INCL);
     }
@@ -261,14 +335,13 @@ __global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
   T out[S][D];
 #pragma unroll
   for (int s = 0; s < S; s++) {
-    const int idx = tid * S + s;
-    if (idx < n_el) {
+    if (tid * S + s < n_el) {
       T t[D];
 #pragma unroll
       for (int i = 0; i < D; i++) {
-        T acc = sb[idx * D + i];
+        T acc = myb[s * D + i];
 #pragma unroll
-        for (int k = 0; k < D; k++) acc += sA[idx * D * D + i * D + k] * z[k];
+        for (int k = 0; k < D; k++) acc += myA[s * D * D + i * D + k] * z[k];
         t[i] = acc;
       }
 #pragma unroll
@@ -278,17 +351,16 @@ __global__ __launch_bounds__((small_nt<D, T>())) void k_scan_small(ScanArgs a) {
       }
     }
   }
-  __syncthreads();  // staging area is rewritten below
+  __syncthreads();  // the b staging area is rewritten with the outputs
 #pragma unroll
   for (int s = 0; s < S; s++) {
-    const int idx = tid * S + s;
-    if (idx < n_el)
+    if (tid * S + s < n_el)
 #pragma unroll
-      for (int i = 0; i < D; i++) sA[idx * D + i] = out[s][i];
+      for (int i = 0; i < D; i++) sb[tid * PB + s * D + i] = out[s][i];
   }
   __syncthreads();
   T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
-  for (int i = tid; i < n_el * D; i += NT) zg[i] = sA[i];
+  stage_out<T, RB, SH::VB, NT>(zg, sb, n_el * D, tid);
 }
 
 // ----------------------------------------------------------- dense d ------
@@ -443,8 +515,8 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
     for (int i = tid; i < D; i += NT) sz[i] = a.z0 ? static_cast<const T*>(a.z0)[seq * D + i] : T(0);
     __syncthreads();
   } else {
-    for (int idx = tid; idx < D * D; idx += NT) aggp[ts * E + idx] = sP[(idx / D) * PS + idx % D];
-    for (int i = tid; i < D; i += NT) aggp[ts * E + D * D + i] = sq[i];
+    for (int idx = tid; idx < D * D; idx += NT) st_payload(aggp + ts * E + idx, sP[(idx / D) * PS + idx % D]);
+    for (int i = tid; i < D; i += NT) st_payload(aggp + ts * E + D * D + i, sq[i]);
     __syncthreads();
     if (tid == 0) publish_flag(flags + ts, FLAG_AGG);
     if (wv == 0) {
@@ -463,11 +535,11 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
     }
     __syncthreads();
     const int64_t j = s_j;
-    for (int i = tid; i < D; i += NT) sz[i] = inclp[j * D + i];
+    for (int i = tid; i < D; i += NT) sz[i] = ld_payload(inclp + j * D + i);
     __syncthreads();
     // the aggregates in between, oldest first, as matrix-vector products
     for (int64_t mm = j + 1; mm < ts; mm++)
-      block_matvec_g<T, D, NT>(aggp + mm * E, aggp + mm * E + D * D, sz, st, false);
+      block_matvec_g<T, D, NT>(aggp + mm * E, aggp + mm * E + D * D, sz, st, true);
   }
   // publish this tile's inclusive prefix: P z_in + q
   {
@@ -478,7 +550,7 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
       for (int k = 0; k < D / QC; k++) part += sP[i * PS + q * (D / QC) + k] * sz[q * (D / QC) + k];
 #pragma unroll
     for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
-    if (i < D && q == 0) inclp[ts * D + i] = part + sq[i];
+    if (i < D && q == 0) st_payload(inclp + ts * D + i, part + sq[i]);
     __syncthreads();
     if (tid == 0) publish_flag(flags + ts, FLAG_INCL);
   }
@@ -498,8 +570,8 @@ static int scan_tile_elems(int d, int dtype, int tile) {
     switch (d) {
 #define PINT_SMALL_TILE(DD)                                                               \
   case DD:                                                                                \
-    return dtype == 0 ? small_nt<DD, double>() * small_s<DD, double>()                    \
-                      : small_nt<DD, float>() * small_s<DD, float>();
+    return dtype == 0 ? SmallShape<DD, double>::TILE                    \
+                      : SmallShape<DD, float>::TILE;
       PINT_SMALL_TILE(1) PINT_SMALL_TILE(2) PINT_SMALL_TILE(3) PINT_SMALL_TILE(4)
       PINT_SMALL_TILE(5) PINT_SMALL_TILE(6) PINT_SMALL_TILE(7) PINT_SMALL_TILE(8)
 #undef PINT_SMALL_TILE
@@ -539,7 +611,7 @@ size_t scan_ws_bytes(int d, int64_t B, int64_t N, int tile, int dtype) {
 
 template <typename T, int D>
 static int launch_small(const ScanArgs& sa, int64_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_scan_small<T, D>), dim3((unsigned)grid), dim3(small_nt<D, T>()), 0, s, sa);
+  hipLaunchKernelGGL((k_scan_small<T, D>), dim3((unsigned)grid), dim3(SmallShape<D, T>::NT), 0, s, sa);
   return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
 }
 
