@@ -68,6 +68,17 @@ def test_dense_tile_sizes(pint, orc):
         _check(pint, orc, 40, 70, 1, "f64", True, seed=7, tile=tile)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_many_tiles_mixed(pint, orc, d, dtype):
+    """Several times more tiles than workgroups resident on the device, three
+    sequences of odd length so that later sequences start misaligned for
+    vector loads and end ragged."""
+    N = 700 * SMALL_TILE[d] + 17
+    print(f"[scan] many tiles d={d} {dtype} N={N} B=3", flush=True)
+    _check(pint, orc, d, N, 3, dtype, True, seed=40 + d)
+
+
 def test_long_sequence(pint, orc):
     """2^20 elements of d = 3: hundreds of tiles in flight at once."""
     _check(pint, orc, 3, 1 << 20, 1, "f64", True, seed=3)
