@@ -91,6 +91,15 @@ typedef struct {
                      /* non-finite) ends the accepted part of the update         */
   int32_t tile;      /* scan tile / chunk hint; 0 = library default              */
   int32_t flags;     /* reserved, must be 0                                      */
+  /* Launch shape of the batched small-d solver (d <= 4); results do not
+   * depend on them.  Dense dimensions require 0 / 0 / NULL. */
+  int32_t block;          /* threads per workgroup: 64, 128 or 256; 0 = 256     */
+  int32_t wg_per_cu;      /* persistent workgroups per compute unit, 1..16;     */
+                          /* 0 = 4                                              */
+  const int64_t* order;   /* device [B]: a permutation of 0..B-1, the order in  */
+                          /* which instances are taken from the work queue      */
+                          /* (e.g. longest first); entries outside [0, B) are   */
+                          /* skipped; NULL = 0, 1, ..., B-1                     */
 } pint_options;
 
 /* Number of parameters of `system` at dimension d, or -1 if not allowed. */
@@ -141,15 +150,38 @@ pint_status pint_solve_varlen(const pint_system* sys, int64_t B, const void* x0,
                               void* ws, size_t ws_bytes, pint_stream_t stream);
 
 /* pint_solve — as pint_solve_varlen with every instance of length T
- * (traj is [B][T][d]).  Single long instances of dense dimension use every
- * compute unit; the host then waits on the stream once per batch of
- * iterations to read the device-side convergence flag, so this call may
- * block until the solve is done. */
+ * (traj is [B][T][d]).  An instance of dense dimension runs on several
+ * workgroups at once (cooperative launch with device-side barriers between
+ * them); like every entry point, the call only enqueues work. */
 pint_status pint_solve(const pint_system* sys, int64_t B, const void* x0,
                        double dt, int64_t T, const pint_options* opts,
                        void* traj, int64_t* iters, double* resid,
                        int32_t* status, void* ws, size_t ws_bytes,
                        pint_stream_t stream);
+
+/*
+ * Executable graph of one batched solve (spec batching requirement:
+ * thousands of uneven-horizon instances in one persistent launch replayed
+ * from a HIP graph).  pint_graph_capture_varlen takes the arguments of
+ * pint_solve_varlen, records the launches that call would enqueue (a fill
+ * kernel that resets the work queue, then the persistent solver; no memset
+ * or memcpy nodes) and instantiates them.  Every pint_graph_launch then
+ * repeats that solve on the same buffers, asynchronously on `stream`: the
+ * caller updates x0 / params / T_off / traj contents in place between
+ * launches, never the pointers or B.  Small dimensions (d <= 4) only;
+ * dense dimensions return PINT_ERR_UNSUPPORTED.  The graph owns no caller
+ * memory; pint_graph_destroy frees the graph objects only.  Errors: the
+ * argument checks of pint_solve_varlen, PINT_ERR_DEVICE if capture or
+ * instantiation fails (*out is then NULL).
+ */
+typedef struct pint_graph_s* pint_graph;
+pint_status pint_graph_capture_varlen(const pint_system* sys, int64_t B, const void* x0,
+                                      double dt, const int64_t* T_off, int64_t T_max,
+                                      const pint_options* opts, void* traj,
+                                      int64_t* iters, double* resid, int32_t* status,
+                                      void* ws, size_t ws_bytes, pint_graph* out);
+pint_status pint_graph_launch(pint_graph graph, pint_stream_t stream);
+pint_status pint_graph_destroy(pint_graph graph);
 
 /* pint_seq_integrate — the sequential comparator x_n = Phi(x_{n-1}),
  * n = 1..T_b, for every instance (eq. explicit-ode with classic RK4).

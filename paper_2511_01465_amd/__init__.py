@@ -44,7 +44,8 @@ class pint_system(C.Structure):
 class pint_options(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("guess", C.c_int32), ("max_iter", C.c_int64),
                 ("window", C.c_int64), ("tol", C.c_double), ("guard", C.c_double),
-                ("tile", C.c_int32), ("flags", C.c_int32)]
+                ("tile", C.c_int32), ("flags", C.c_int32), ("block", C.c_int32),
+                ("wg_per_cu", C.c_int32), ("order", C.c_void_p)]
 
 
 _lib = None
@@ -52,7 +53,8 @@ _lib = None
 EXPORTS = ["pint_n_params", "pint_status_string", "pint_supported", "pint_workspace_bytes",
            "pint_solve_varlen", "pint_solve", "pint_seq_integrate", "pint_residual",
            "pint_elements", "pint_scan_workspace_bytes", "pint_affine_scan",
-           "pint_adjoint_workspace_bytes", "pint_adjoint"]
+           "pint_adjoint_workspace_bytes", "pint_adjoint", "pint_graph_capture_varlen",
+           "pint_graph_launch", "pint_graph_destroy"]
 
 
 def load(path: str = LIB_PATH):
@@ -79,6 +81,10 @@ def load(path: str = LIB_PATH):
         "pint_affine_scan": (C.c_int, [i32, i64, i64, i32, vp, vp, vp, vp, i32, vp, sz, vp]),
         "pint_adjoint_workspace_bytes": (sz, [SP, i64, i64, i64, i32]),
         "pint_adjoint": (C.c_int, [SP, i64, vp, dbl, i64, i32, vp, vp, vp, vp, i64, vp, sz, vp]),
+        "pint_graph_capture_varlen": (C.c_int, [SP, i64, vp, dbl, vp, i64, OP, vp, vp, vp, vp, vp, sz,
+                                                C.POINTER(C.c_void_p)]),
+        "pint_graph_launch": (C.c_int, [vp, vp]),
+        "pint_graph_destroy": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -136,9 +142,11 @@ def make_system(system: int, d: int, params: torch.Tensor, shared: bool) -> pint
 
 
 def make_options(dtype: int, tol: float = 1e-10, window: int = 0, max_iter: int = 0,
-                 guess: int = 0, guard: float = 1e6, tile: int = 0) -> pint_options:
+                 guess: int = 0, guard: float = 1e6, tile: int = 0, block: int = 0,
+                 wg_per_cu: int = 0, order: Optional[torch.Tensor] = None) -> pint_options:
+    """`order` (device int64 [B]) must stay alive while the options are used."""
     return pint_options(dtype, guess, int(max_iter), int(window), float(tol), float(guard),
-                        int(tile), 0)
+                        int(tile), 0, int(block), int(wg_per_cu), _ptr(order))
 
 
 def _sys_id(system) -> int:
@@ -210,6 +218,25 @@ def pint_adjoint(sysd, B, x0, dt, T, dtype, traj, g, dL_dx0, dL_dtheta, seg, ws,
                                0 if ws is None else ws.numel(), _stream(stream))
 
 
+def pint_graph_capture_varlen(sysd, B, x0, dt, T_off, T_max, opts, traj, iters, resid, status,
+                              ws):
+    """Returns (status, handle); handle is None unless status is OK."""
+    h = C.c_void_p()
+    rc = load().pint_graph_capture_varlen(C.byref(sysd), B, _ptr(x0), dt, _ptr(T_off), T_max,
+                                          C.byref(opts), _ptr(traj), _ptr(iters), _ptr(resid),
+                                          _ptr(status), _ptr(ws), 0 if ws is None else ws.numel(),
+                                          C.byref(h))
+    return rc, (h.value if rc == OK else None)
+
+
+def pint_graph_launch(handle, stream=None) -> int:
+    return load().pint_graph_launch(handle, _stream(stream))
+
+
+def pint_graph_destroy(handle) -> int:
+    return load().pint_graph_destroy(handle)
+
+
 # ---------------------------------------------------------- conveniences --
 
 def _workspace(nbytes: int, device) -> Optional[torch.Tensor]:
@@ -247,12 +274,25 @@ def solve(system, x0: torch.Tensor, params: torch.Tensor, dt: float, T: int, *,
     return traj, iters, resid, status
 
 
+def longest_first(lengths, device) -> torch.Tensor:
+    """Instance order for the work queue: longest horizon first (a stable
+    sort), so the longest solves start early and the batch ends evenly."""
+    lengths = torch.as_tensor(lengths, dtype=torch.int64).cpu()
+    return torch.argsort(-lengths, stable=True).to(device)
+
+
 def solve_varlen(system, x0: torch.Tensor, params: torch.Tensor, dt: float, lengths, *,
                  tol: float = 1e-10, window: int = 0, max_iter: int = 0, guess=None,
-                 guard: float = 1e6, tile: int = 0, stream=None):
+                 guard: float = 1e6, tile: int = 0, block: int = 0, wg_per_cu: int = 0,
+                 order=None, stream=None):
     """Newton solve of B instances with their own horizons `lengths` [B].
+    `order`: None, "longest_first", or a device int64 permutation [B].
     Returns (traj [sum T, d] packed, T_off [B+1], iters, resid, status)."""
     sid = _sys_id(system)
+    if isinstance(order, str):
+        if order != "longest_first":
+            raise PintError(f"unknown order {order!r}")
+        order = longest_first(lengths, x0.device)
     x0 = x0.contiguous()
     B, d = x0.shape
     prm, shared = _params_2d(params.to(x0.dtype), B, n_params(sid, d))
@@ -270,11 +310,66 @@ def solve_varlen(system, x0: torch.Tensor, params: torch.Tensor, dt: float, leng
     status = torch.empty(B, dtype=torch.int32, device=x0.device)
     sysd = make_system(sid, d, prm, shared)
     opts = make_options(_dtype_code(x0), tol, window, max_iter, 1 if guess is not None else 0,
-                        guard, tile)
+                        guard, tile, block, wg_per_cu, order)
     ws = _workspace(pint_workspace_bytes(sysd, B, total, T_max, opts), x0.device)
     _check(pint_solve_varlen(sysd, B, x0, float(dt), T_off, T_max, opts, traj, iters, resid,
                              status, ws, stream), "pint_solve_varlen")
     return traj, T_off, iters, resid, status
+
+
+class SolveGraph:
+    """A batched solve captured once as an executable HIP graph
+    (pint_graph_capture_varlen) and replayed with `launch()`.  The buffers
+    are owned here and fixed for the graph's life: write new initial states
+    into `x0`, `params` (or `traj` with guess=True) in place between
+    launches; results are in `traj`, `iters`, `resid`, `status`."""
+
+    def __init__(self, system, x0: torch.Tensor, params: torch.Tensor, dt: float, lengths, *,
+                 tol: float = 1e-10, window: int = 0, max_iter: int = 0, guess: bool = False,
+                 guard: float = 1e6, block: int = 0, wg_per_cu: int = 0, order=None):
+        sid = _sys_id(system)
+        self.x0 = x0.contiguous().clone()
+        B, d = self.x0.shape
+        self.params, shared = _params_2d(params.to(x0.dtype).clone(), B, n_params(sid, d))
+        lengths = torch.as_tensor(lengths, dtype=torch.int64).cpu()
+        T_off_h = torch.zeros(B + 1, dtype=torch.int64)
+        T_off_h[1:] = torch.cumsum(lengths, 0)
+        self.T_off = T_off_h.to(x0.device)
+        total, T_max = int(T_off_h[-1]), int(lengths.max()) if B else 0
+        if isinstance(order, str):
+            if order != "longest_first":
+                raise PintError(f"unknown order {order!r}")
+            order = longest_first(lengths, x0.device)
+        self.order = order
+        self.traj = torch.empty((total, d), dtype=x0.dtype, device=x0.device)
+        self.iters = torch.empty(B, dtype=torch.int64, device=x0.device)
+        self.resid = torch.empty(B, dtype=torch.float64, device=x0.device)
+        self.status = torch.empty(B, dtype=torch.int32, device=x0.device)
+        self._sysd = make_system(sid, d, self.params, shared)
+        self._opts = make_options(_dtype_code(x0), tol, window, max_iter, 1 if guess else 0, guard,
+                                  0, block, wg_per_cu, order)
+        self.ws = _workspace(pint_workspace_bytes(self._sysd, B, total, T_max, self._opts), x0.device)
+        torch.cuda.synchronize(x0.device)
+        rc, self._h = pint_graph_capture_varlen(self._sysd, B, self.x0, float(dt), self.T_off, T_max,
+                                                self._opts, self.traj, self.iters, self.resid,
+                                                self.status, self.ws)
+        _check(rc, "pint_graph_capture_varlen")
+
+    def launch(self, stream=None):
+        if self._h is None:
+            raise PintError("graph destroyed")
+        _check(pint_graph_launch(self._h, stream), "pint_graph_launch")
+
+    def close(self):
+        if self._h is not None:
+            pint_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def seq_integrate(system, x0: torch.Tensor, params: torch.Tensor, dt: float, lengths, stream=None):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <new>
 
 #include "../../include/pint.h"
 #include "internal.h"
@@ -41,6 +42,8 @@ int check_opts(const pint_options* o) {
   if (o->dtype != PINT_F64 && o->dtype != PINT_F32) return PINT_ERR_INVALID_ARG;
   if (o->guess != 0 && o->guess != 1) return PINT_ERR_INVALID_ARG;
   if (o->window < 0 || o->flags != 0 || o->tile < 0) return PINT_ERR_INVALID_ARG;
+  if (o->block != 0 && o->block != 64 && o->block != 128 && o->block != 256) return PINT_ERR_INVALID_ARG;
+  if (o->wg_per_cu < 0 || o->wg_per_cu > 16) return PINT_ERR_INVALID_ARG;
   if (!(o->tol > 0.0) || std::isnan(o->guard) || !(o->guard > 0.0)) return PINT_ERR_INVALID_ARG;
   return PINT_OK;
 }
@@ -69,6 +72,9 @@ SolveArgs make_args(const pint_system* sys, int64_t B, const void* x0, double dt
     a.max_iter = o->max_iter > 0 ? o->max_iter : T_max + 1;
     a.guess = o->guess;
     a.tile = o->tile;
+    a.block = o->block;
+    a.wg_per_cu = o->wg_per_cu;
+    a.order = o->order;
   }
   a.iters = iters;
   a.resid = resid;
@@ -132,6 +138,7 @@ static pint_status solve_common(const pint_system* sys, int64_t B, const void* x
     rc = small_solve(a);
   } else {
     if (T_off) return PINT_ERR_UNSUPPORTED;  // dense dimensions: uniform batches only
+    if (opts->block != 0 || opts->wg_per_cu != 0 || opts->order) return PINT_ERR_UNSUPPORTED;
     rc = dense_solve(a);
   }
   return (pint_status)rc;
@@ -151,6 +158,68 @@ pint_status pint_solve(const pint_system* sys, int64_t B, const void* x0, double
                        int32_t* status, void* ws, size_t ws_bytes, pint_stream_t stream) {
   return solve_common(sys, B, x0, dt, nullptr, T, T, opts, traj, iters, resid, status, ws,
                       ws_bytes, stream);
+}
+
+}  // extern "C"
+
+struct pint_graph_s {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" {
+
+pint_status pint_graph_capture_varlen(const pint_system* sys, int64_t B, const void* x0, double dt,
+                                      const int64_t* T_off, int64_t T_max, const pint_options* opts,
+                                      void* traj, int64_t* iters, double* resid, int32_t* status,
+                                      void* ws, size_t ws_bytes, pint_graph* out) {
+  if (!out) return PINT_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!T_off) return PINT_ERR_INVALID_ARG;
+  if (int rc = check_sys(sys, B)) return (pint_status)rc;
+  if (int rc = check_opts(opts)) return (pint_status)rc;
+  if (!is_small(sys->system, sys->d)) return PINT_ERR_UNSUPPORTED;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return PINT_ERR_DEVICE;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return PINT_ERR_DEVICE;
+  }
+  const pint_status rc = solve_common(sys, B, x0, dt, T_off, 0, T_max, opts, traj, iters, resid,
+                                      status, ws, ws_bytes, reinterpret_cast<pint_stream_t>(cs));
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &g);  // always end the capture
+  (void)hipStreamDestroy(cs);
+  if (rc != PINT_OK || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != PINT_OK ? rc : PINT_ERR_DEVICE;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess || !ex) {
+    (void)hipGraphDestroy(g);
+    return PINT_ERR_DEVICE;
+  }
+  pint_graph h = new (std::nothrow) pint_graph_s{g, ex};
+  if (!h) {
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
+    return PINT_ERR_DEVICE;
+  }
+  *out = h;
+  return PINT_OK;
+}
+
+pint_status pint_graph_launch(pint_graph graph, pint_stream_t stream) {
+  if (!graph || !graph->exec) return PINT_ERR_INVALID_ARG;
+  return hipGraphLaunch(graph->exec, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? PINT_OK
+                                                                                          : PINT_ERR_DEVICE;
+}
+
+pint_status pint_graph_destroy(pint_graph graph) {
+  if (!graph) return PINT_ERR_INVALID_ARG;
+  const bool ok = hipGraphExecDestroy(graph->exec) == hipSuccess && hipGraphDestroy(graph->graph) == hipSuccess;
+  delete graph;
+  return ok ? PINT_OK : PINT_ERR_DEVICE;
 }
 
 pint_status pint_seq_integrate(const pint_system* sys, int64_t B, const void* x0, double dt,

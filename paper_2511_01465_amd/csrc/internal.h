@@ -22,6 +22,9 @@ struct SolveArgs {
   int64_t window, max_iter;
   int32_t guess;
   int32_t tile;
+  int32_t block;          // batched small-d solver: threads per workgroup (0 = 256)
+  int32_t wg_per_cu;      // batched small-d solver: persistent workgroups per CU (0 = 4)
+  const int64_t* order;   // [B] order in which instances are taken, or nullptr
   int64_t* iters;
   double* resid;
   int32_t* status;

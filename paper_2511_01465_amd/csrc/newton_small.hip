@@ -9,7 +9,9 @@
 
 namespace pint {
 
-constexpr int NT_SMALL = 256;  // threads per workgroup = steps per chunk
+// Threads per workgroup = steps per chunk of the in-workgroup scan: 64, 128
+// or 256 (a launch-shape choice; results do not depend on it).
+constexpr int NT_SMALL = 256;
 
 struct SmallKArgs {
   int64_t B;
@@ -26,6 +28,7 @@ struct SmallKArgs {
   double* resid;
   int32_t* status;
   uint32_t* queue;
+  const int64_t* order;  // [B] instance taken at each queue slot, or nullptr
 };
 
 template <typename T, int D>
@@ -54,9 +57,9 @@ __device__ __forceinline__ double step_resid(const T* P, T dt, const T* X, const
   return m;
 }
 
-template <typename T, class S>
-__global__ __launch_bounds__(NT_SMALL) void k_newton_small(SmallKArgs a) {
-  constexpr int D = S::D, NP = S::NP, NT = NT_SMALL;
+template <typename T, class S, int NT>
+__global__ __launch_bounds__(NT) void k_newton_small(SmallKArgs a) {
+  constexpr int D = S::D, NP = S::NP;
   __shared__ Aff<T, D> s_aff[NT / PINT_WAVE];
   __shared__ double s_red[NT / PINT_WAVE];
   __shared__ int64_t s_redi[NT / PINT_WAVE];
@@ -69,9 +72,11 @@ __global__ __launch_bounds__(NT_SMALL) void k_newton_small(SmallKArgs a) {
   for (;;) {
     if (tid == 0) s_slot = atomicAdd(a.queue, 1u);
     __syncthreads();
-    const int64_t inst = s_slot;
+    const int64_t slot = s_slot;
     __syncthreads();
-    if (inst >= a.B) break;
+    if (slot >= a.B) break;
+    const int64_t inst = a.order ? a.order[slot] : slot;
+    if (inst < 0 || inst >= a.B) continue;  // not a permutation entry: skipped
 
     const int64_t t0 = a.T_off ? a.T_off[inst] : inst * a.T_uniform;
     const int64_t Tn = (a.T_off ? a.T_off[inst + 1] : t0 + a.T_uniform) - t0;
@@ -351,6 +356,7 @@ static SmallKArgs to_k(const SolveArgs& a) {
   k.iters = a.iters;
   k.resid = a.resid;
   k.status = a.status;
+  k.order = a.order;
   return k;
 }
 
@@ -364,14 +370,20 @@ int small_solve(const SolveArgs& a) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int64_t want = (int64_t)cus * 4;
+  const int64_t want = (int64_t)cus * (a.wg_per_cu > 0 ? a.wg_per_cu : 4);
   const int grid = (int)(a.B < want ? a.B : want);
   if (grid <= 0) return ST_OK;
+  const int nt = a.block > 0 ? a.block : NT_SMALL;
   return dispatch_small(a.dtype, a.system, a.d, [&](auto t, auto s) {
     using T = decltype(t);
     using S = decltype(s);
-    hipLaunchKernelGGL((k_newton_small<T, S>), dim3(grid), dim3(NT_SMALL), 0, a.stream, k);
-    return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
+    switch (nt) {
+      case 64: hipLaunchKernelGGL((k_newton_small<T, S, 64>), dim3(grid), dim3(64), 0, a.stream, k); break;
+      case 128: hipLaunchKernelGGL((k_newton_small<T, S, 128>), dim3(grid), dim3(128), 0, a.stream, k); break;
+      case 256: hipLaunchKernelGGL((k_newton_small<T, S, 256>), dim3(grid), dim3(256), 0, a.stream, k); break;
+      default: return (int)ST_INVALID;
+    }
+    return hipGetLastError() == hipSuccess ? (int)ST_OK : (int)ST_DEVICE;
   });
 }
 

@@ -54,3 +54,48 @@ def test_host_side_queries_without_gpu():
     rc = lib.pint_solve(ctypes.byref(sysd), 0, None, 1e-3, 16, ctypes.byref(opts),
                         None, None, None, None, None, 0, None)
     assert rc == P.OK   # empty batch: nothing to do
+
+
+def test_options_layout_matches_the_header(tmp_path):
+    """The ctypes mirror of pint_options has the C layout (size and field
+    offsets from a program compiled against include/pint.h)."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("no C compiler")
+    import paper_2511_01465_amd as P
+    src = tmp_path / "layout.c"
+    fields = [f[0] for f in P.pint_options._fields_]
+    body = " ".join('printf("%%zu ", offsetof(pint_options, %s));' % f for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pint.h"\n'
+                   'int main(void){printf("%%zu ", sizeof(pint_options)); %s return 0;}\n' % body)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(P.pint_options)] + [getattr(P.pint_options, f).offset for f in fields]
+    assert got == want
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpint.so not built")
+def test_launch_shape_and_graph_argument_checks():
+    import paper_2511_01465_amd as P
+    lib = P.load()
+    sysd = P.pint_system(P.VDP, 2, 1, 1, None)
+    for kw in ({"block": 96}, {"wg_per_cu": 17}, {"wg_per_cu": -1}):
+        opts = P.make_options(P.F64, **kw)
+        rc = lib.pint_solve(ctypes.byref(sysd), 0, None, 1e-2, 16, ctypes.byref(opts),
+                            None, None, None, None, None, 0, None)
+        assert rc == P.ERR_INVALID_ARG, kw
+    # graph capture: a missing handle pointer or offsets is refused before any HIP call
+    opts = P.make_options(P.F64)
+    assert lib.pint_graph_capture_varlen(ctypes.byref(sysd), 0, None, 1e-2, None, 0,
+                                         ctypes.byref(opts), None, None, None, None, None, 0,
+                                         None) == P.ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    assert lib.pint_graph_capture_varlen(ctypes.byref(sysd), 0, None, 1e-2, None, 0,
+                                         ctypes.byref(opts), None, None, None, None, None, 0,
+                                         ctypes.byref(h)) == P.ERR_INVALID_ARG
+    assert h.value is None
+    assert lib.pint_graph_launch(None, None) == P.ERR_INVALID_ARG
+    assert lib.pint_graph_destroy(None) == P.ERR_INVALID_ARG
