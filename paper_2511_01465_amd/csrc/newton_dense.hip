@@ -148,7 +148,12 @@ __device__ __forceinline__ void dn_elements(DenseSmem<T, S>& sm, T dt, const T* 
     for (int t = tid; t < SPP * JT; t += NT) {
       const int sl = t / JT, sub = t % JT;
       const int64_t m = g0 + sl * m_stride;
-      if (m < len) S::jac_thread(&sm.stage[sl], sm.P, sub, dt, AT + m * D * D, 1, D);
+      if (m < len) {
+        if constexpr (S::BANDED)
+          S::jac_band_thread(&sm.stage[sl], sm.P, sub, dt, AT + m * S::BW * D);
+        else
+          S::jac_thread(&sm.stage[sl], sm.P, sub, dt, AT + m * D * D, 1, D);
+      }
     }
     __syncthreads();
   }
@@ -235,6 +240,151 @@ __device__ __forceinline__ int64_t dn_fold(DenseSmem<T, S>& sm, const T* AT, con
   return q == INT64_MAX ? len : q;
 }
 
+// Banded systems: the window's Newton step from band-stored Jacobians.
+// The folding workgroup stages the window through LDS in chunks of CH steps,
+// double-buffered: while wave 0 runs the recursion over chunk c (lane i owns
+// row i: BW multiply-adds, the previous step's dx exchanged by wave
+// shuffles, no workgroup barrier per step), waves 1.. copy chunk c+1 from
+// the workspace (written by other compute units) with all loads in flight.
+template <class S>
+struct BandShape {
+  static constexpr int CH = 12;                     // steps per chunk
+  static constexpr int NB = S::BW * S::D;            // band scalars per step
+  static constexpr int PER = NB + 2 * S::D;          // per step: band, b, old x
+};
+
+template <typename T, class S>
+constexpr size_t band_lds_bytes() {
+  if constexpr (S::BANDED)
+    return 2 * (size_t)BandShape<S>::CH * BandShape<S>::PER * sizeof(T);
+  else
+    return 0;
+}
+
+// Copy n consecutive scalars from global src to LDS dst with threads
+// t, t+nt, ...: 16-byte vectors when both ends are aligned, MAXV loads per
+// thread issued before their LDS stores.
+template <typename T, int MAXV>
+__device__ __forceinline__ void lds_copy(T* dst, const T* __restrict__ src, int n, int t, int nt) {
+  constexpr int V = 16 / sizeof(T);
+  typedef T v_t __attribute__((ext_vector_type(V)));
+  const bool vec = (reinterpret_cast<uintptr_t>(src) % 16 == 0) && (reinterpret_cast<uintptr_t>(dst) % 16 == 0);
+  if (vec) {
+    const int nv = n / V;
+    for (int v0 = 0; v0 < nv; v0 += MAXV * nt) {
+      v_t r[MAXV];
+#pragma unroll
+      for (int u = 0; u < MAXV; u++) {
+        const int v = v0 + u * nt + t;
+        if (v < nv) r[u] = reinterpret_cast<const v_t*>(src)[v];
+      }
+#pragma unroll
+      for (int u = 0; u < MAXV; u++) {
+        const int v = v0 + u * nt + t;
+        if (v < nv) reinterpret_cast<v_t*>(dst)[v] = r[u];
+      }
+    }
+    for (int q = nv * V + t; q < n; q += nt) dst[q] = src[q];
+  } else {
+    for (int q0 = 0; q0 < n; q0 += MAXV * nt) {
+      T r[MAXV];
+#pragma unroll
+      for (int u = 0; u < MAXV; u++) {
+        const int q = q0 + u * nt + t;
+        if (q < n) r[u] = src[q];
+      }
+#pragma unroll
+      for (int u = 0; u < MAXV; u++) {
+        const int q = q0 + u * nt + t;
+        if (q < n) dst[q] = r[u];
+      }
+    }
+  }
+}
+
+template <typename T, class S>
+__device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, const T* Bd, const T* bb,
+                                                const T* Xw, T* xnb, int64_t len, bool plain, double guard) {
+  constexpr int D = S::D, NT = S::NT, BW = S::BW, BOFF = S::BOFF;
+  using BS = BandShape<S>;
+  constexpr int CH = BS::CH, NB = BS::NB, PER = BS::PER;
+  static_assert(D <= PINT_WAVE && NT > PINT_WAVE, "one wave owns the rows");
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  const int nl = NT - PINT_WAVE, lt = tid - PINT_WAVE;  // loader threads (waves 1..)
+  // chunk in half h: [CH][NB] band, then [CH][D] b, then [CH][D] old x
+  constexpr int V = 16 / sizeof(T), NL = NT - PINT_WAVE;
+  constexpr int MVB = (CH * NB / V + NL - 1) / NL, MVX = (CH * D / V + NL - 1) / NL;
+  auto load = [&](int64_t c0, int n, int h) {
+    T* dst = lbuf + (size_t)h * CH * PER;
+    lds_copy<T, MVB>(dst, Bd + c0 * NB, n * NB, lt, nl);
+    lds_copy<T, MVX>(dst + CH * NB, bb + c0 * D, n * D, lt, nl);
+    lds_copy<T, MVX>(dst + CH * NB + CH * D, Xw + c0 * D, n * D, lt, nl);
+  };
+  const int64_t nch = (len + CH - 1) / CH;
+  if (wv > 0 && len > 0) load(0, (int)(len < CH ? len : CH), 0);
+  lds_barrier();  // the chunks travel through LDS only
+  // wave 0: lane i < D owns row i.  The previous step's dx goes through LDS
+  // as zx[p] = dx[(p - BOFF) mod D], p < D + BW - 1, so row i reads the
+  // consecutive zx[i .. i+BW-1] (one wave writes and reads: in order).
+  static_assert(D + BW - 1 <= 2 * D, "zx fits in sm.z");
+  T* zx = &sm.z[0][0];
+  const int i = lane < D ? lane : 0;
+  int64_t bad = INT64_MAX;
+  for (int64_t c = 0; c < nch; c++) {
+    const int64_t c0 = c * CH;
+    const int n = (int)((len - c0) < CH ? (len - c0) : CH);
+    if (wv > 0) {
+      if (c + 1 < nch) {
+        const int64_t c1 = c0 + CH;
+        load(c1, (int)((len - c1) < CH ? (len - c1) : CH), (int)((c + 1) & 1));
+      }
+    } else if (bad == INT64_MAX) {
+      const T* L = lbuf + (size_t)(c & 1) * CH * PER;
+      for (int m = 0; m < n; m++) {
+        const T* band = L + m * NB;
+        T a0 = L[CH * NB + m * D + i], a1 = T(0);
+        if (c0 + m > 0) {
+          // issue all LDS reads of the step, then the multiply-adds
+          T bv[BW], zv[BW];
+#pragma unroll
+          for (int k = 0; k < BW; k++) {
+            bv[k] = band[k * D + i];
+            zv[k] = zx[i + k];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int k = 0; k < BW; k++) {
+            if (k & 1)
+              a1 += bv[k] * zv[k];
+            else
+              a0 += bv[k] * zv[k];
+          }
+        }
+        const T z = a0 + a1;
+        if (lane < D) {
+          zx[i + BOFF] = z;
+          if (i >= D - BOFF) zx[i + BOFF - D] = z;
+          if (i + BOFF + D < D + BW - 1) zx[i + BOFF + D] = z;
+        }
+        const T xn = L[CH * NB + CH * D + m * D + i] + z;
+        if (lane < D) {
+          xnb[(c0 + m) * D + i] = xn;
+          if (!plain && (!finite_(xn) || fabs((double)xn) > guard)) bad = c0 + m;
+        }
+        // the first cut step ends the fold (later states are not used)
+        if (!plain && __ballot(bad != INT64_MAX)) break;
+      }
+      bad = wave_min_i64(lane < D ? bad : INT64_MAX);
+    }
+    lds_barrier();  // chunk c+1 staged, chunk c folded
+  }
+  if (tid == 0) sm.redi[0] = bad;
+  __syncthreads();  // also: wave 0's updated states are visible to dn_commit
+  const int64_t q = sm.redi[0];
+  __syncthreads();
+  return q == INT64_MAX ? len : q;
+}
+
 // Write the accepted part [0, q) of the updated window states.
 template <typename T, class S>
 __device__ __forceinline__ void dn_commit(T* Xw, const T* xnb, int64_t q) {
@@ -257,6 +407,8 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense(DenseKArgs a) {
   constexpr int D = S::D, NT = S::NT;
   __shared__ DenseSmem<T, S> sm;
   __shared__ uint32_t s_slot;
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  T* band_buf = reinterpret_cast<T*>(dyn_lds);  // band_lds_bytes<T, S>() bytes
   const int tid = threadIdx.x;
   const T dt = (T)a.dt;
   T* slot = static_cast<T*>(a.ws_elems) + (int64_t)blockIdx.x * a.slot_stride;
@@ -302,7 +454,11 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense(DenseKArgs a) {
       }
       const int64_t len = hi - lo + 1;
       dn_elements<T, S>(sm, dt, X, lo, len, 0, 1, AT, bb);
-      const int64_t q = dn_fold<T, S>(sm, AT, bb, X + (lo - 1) * D, dxb, len, plain, a.guard);
+      int64_t q;
+      if constexpr (S::BANDED)
+        q = dn_fold_band<T, S>(sm, band_buf, AT, bb, X + (lo - 1) * D, dxb, len, plain, a.guard);
+      else
+        q = dn_fold<T, S>(sm, AT, bb, X + (lo - 1) * D, dxb, len, plain, a.guard);
       dn_commit<T, S>(X + (lo - 1) * D, dxb, q);
       if (q == 0) { st = ST_NONFINITE; break; }
       k++;
@@ -369,6 +525,8 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
   constexpr int D = S::D, NT = S::NT;
   __shared__ DenseSmem<T, S> sm;
   __shared__ int64_t s_win[2];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  T* band_buf = reinterpret_cast<T*>(dyn_lds);  // band_lds_bytes<T, S>() bytes
   __shared__ int32_t s_done;
   const int tid = threadIdx.x;
   const int64_t inst = blockIdx.x / G;
@@ -431,7 +589,11 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
     dn_elements<T, S>(sm, dt, X, lo, len, g, G, AT, bb);
     coop_barrier(c, G, gen);
     if (g == 0) {
-      const int64_t q = dn_fold<T, S>(sm, AT, bb, X + (lo - 1) * D, dxb, len, false, a.guard);
+      int64_t q;
+      if constexpr (S::BANDED)
+        q = dn_fold_band<T, S>(sm, band_buf, AT, bb, X + (lo - 1) * D, dxb, len, false, a.guard);
+      else
+        q = dn_fold<T, S>(sm, AT, bb, X + (lo - 1) * D, dxb, len, false, a.guard);
       dn_commit<T, S>(X + (lo - 1) * D, dxb, q);
       if (q == 0) {
         st = ST_NONFINITE;
@@ -632,7 +794,8 @@ static int coop_groups(const SolveArgs& a) {
   int64_t G = (W + S::SPP - 1) / S::SPP;
   if (G > 64) G = 64;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_newton_dense_coop<T, S>, S::NT, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_newton_dense_coop<T, S>, S::NT,
+                                                   band_lds_bytes<T, S>()) != hipSuccess)
     return 1;
   const int64_t cap = (int64_t)per_cu * num_cus();
   while (G > 1 && a.B * G > cap) G--;
@@ -683,16 +846,26 @@ int dense_solve(const SolveArgs& a) {
     CoopCtl* ctl = reinterpret_cast<CoopCtl*>(w + l.ctl_off);
     // queue counter and control blocks start at zero (a kernel, not a memset)
     if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w), l.slots_off / 4, 0u, a.stream)) return rc;
+    const size_t lds = band_lds_bytes<T, S>();
+    static bool attr_set = false;  // per (T, S) instantiation
+    if (!attr_set && lds > 0) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_newton_dense_coop<T, S>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+          hipFuncSetAttribute(reinterpret_cast<const void*>(&k_newton_dense<T, S>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return ST_DEVICE;
+      attr_set = true;
+    }
     const int G = coop_groups<T, S>(a);
     if (G >= 2) {
       int Gv = G;
       void* args[] = {&k, &Gv, &ctl};
       const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_newton_dense_coop<T, S>),
-                                                      dim3((unsigned)(a.B * G)), dim3(S::NT), args, 0, a.stream);
+                                                      dim3((unsigned)(a.B * G)), dim3(S::NT), args, lds, a.stream);
       if (e == hipSuccess) return ST_OK;
       (void)hipGetLastError();  // fall back to one workgroup per instance
     }
-    hipLaunchKernelGGL((k_newton_dense<T, S>), dim3(dense_grid(a.B)), dim3(S::NT), 0, a.stream, k);
+    hipLaunchKernelGGL((k_newton_dense<T, S>), dim3(dense_grid(a.B)), dim3(S::NT), lds, a.stream, k);
     return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
   });
 }

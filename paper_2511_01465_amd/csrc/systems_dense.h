@@ -34,6 +34,13 @@ struct DSysL96 {
   static constexpr int SPP = NT >= JT ? NT / JT : 1;  // steps per Jacobian pass
   using Stage = StageL96<T, D>;
   static_assert(D >= 4 && D <= 64 && D % QB == 0 && RB >= 2, "Lorenz-96 dense path");
+  // J = dPhi/dx is banded: f_i reads x_{i-2..i+1}, so the four chained stage
+  // Jacobians of RK4 reach only j - i in [-8, 4] (cyclic); every other entry
+  // is exactly zero.  Band storage: diagonal k = (j - i + BOFF) mod D,
+  // k < BW, at band[k * D + i].
+  static constexpr bool BANDED = true;
+  static constexpr int BW = 13, BOFF = 8;
+  static_assert(D >= 2 * BW, "band must not wrap onto itself");
 
   __device__ static void f(const T* P, const T (&x)[R], T (&out)[R], int lane) {
     const int i = lane < D ? lane : 0;
@@ -54,6 +61,16 @@ struct DSysL96 {
   //   (Jf u)_i = x_{i-1}(u_{i+1} - u_{i-2}) + (x_{i+1} - x_{i-2}) u_{i-1} - u_i,
   // each thread needs u_{r0-2}, u_{r0-1} and u_{r0+RB} from its neighbours.
   __device__ static void jac_thread(const Stage* st, const T*, int sub, T dt, T* out, int rs, int cs) {
+    T col[RB];
+    jac_column(st, sub, dt, col);
+    const int j = sub / QB, r0 = (sub % QB) * RB;
+    T* o = out + j * cs;
+#pragma unroll
+    for (int k = 0; k < RB; k++) o[(r0 + k) * rs] = col[k];
+  }
+
+  // Rows [r0, r0+RB) of column j = sub/QB of J (r0 = (sub%QB)*RB).
+  __device__ static void jac_column(const Stage* st, int sub, T dt, T (&col)[RB]) {
     const int j = sub / QB, q = sub % QB, r0 = q * RB;
     const int lane = threadIdx.x % PINT_WAVE, base = lane - q;
     const int nxt = base + (q + 1) % QB, prv = base + (q + QB - 1) % QB;
@@ -86,9 +103,23 @@ struct DSysL96 {
         um1 = uk;
       }
     }
-    T* o = out + j * cs;
 #pragma unroll
-    for (int k = 0; k < RB; k++) o[(r0 + k) * rs] = ((r0 + k == j) ? T(1) : T(0)) + c6 * acc[k];
+    for (int k = 0; k < RB; k++) col[k] = ((r0 + k == j) ? T(1) : T(0)) + c6 * acc[k];
+  }
+
+  // As jac_thread, storing only the band (see BW): element (i, j) with
+  // k = (j - i + BOFF) mod D < BW goes to band[k * D + i].
+  __device__ static void jac_band_thread(const Stage* st, const T* P, int sub, T dt, T* band) {
+    T col[RB];
+    jac_column(st, sub, dt, col);
+    const int j = sub / QB, r0 = (sub % QB) * RB;
+#pragma unroll
+    for (int k = 0; k < RB; k++) {
+      const int i = r0 + k;
+      int kb = j - i + BOFF;
+      kb = kb < 0 ? kb + D : (kb >= D ? kb - D : kb);
+      if (kb < BW) band[kb * D + i] = col[k];
+    }
   }
 };
 
@@ -106,6 +137,8 @@ struct DSysKur {
   static constexpr int SPP = NT >= JT ? NT / JT : 1;
   using Stage = StageKur<T, D>;
   static_assert(D % 64 == 0 && D % QB == 0, "Kuramoto dense path: d a multiple of 64");
+  static constexpr bool BANDED = false;  // all-to-all coupling: J is dense
+  static constexpr int BW = 0, BOFF = 0;
 
   __device__ static void sums(const T (&x)[R], T (&sn)[R], T (&cs)[R], T& S, T& C, int lane) {
     T ls = T(0), lc = T(0);
