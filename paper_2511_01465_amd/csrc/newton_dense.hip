@@ -26,15 +26,27 @@ struct DenseKArgs {
   double* resid;
   int32_t* status;
   uint32_t* queue;
-  void* ws_elems;        // per workgroup slot: AT [Wt][D][D], b [Wt][D], dx [Wt][D]
-  int64_t Wt;            // elements per slot (window length, or T in plain mode)
+  void* ws_elems;        // per workgroup slot: AT [Wt][D][D], b [Wt][D], dx [Wt][D], hn [Wt]
+  int64_t Wt;            // elements per slot (window + slack, or T in plain mode)
   int64_t slot_stride;   // scalars between consecutive workgroup slots
 };
 
+// Slot: AT [Wt][D][D] (or the band), b [Wt][D], dx [Wt][D], then the
+// per-step residual norms hn [Wt] (double, 8-byte aligned).
+template <class S>
+__host__ __device__ constexpr int64_t slot_hn_offset(int64_t Wt) {
+  return (Wt * (int64_t)S::D * S::D + 2 * Wt * (int64_t)S::D + 1) / 2 * 2;
+}
 template <class S>
 __host__ __device__ constexpr int64_t slot_scalars(int64_t Wt) {
-  return Wt * (int64_t)S::D * S::D + 2 * Wt * (int64_t)S::D;
+  return slot_hn_offset<S>(Wt) + 2 * Wt;  // hn in doubles (2 scalars of float each)
 }
+
+// Speculative slack of the cooperative solver: each update builds the
+// elements of W + SPEC_SLACK steps from the current first violation, so the
+// next first violation (which moves ahead a few steps per update) is read off
+// their residuals instead of being searched for separately.
+constexpr int64_t SPEC_SLACK = 32;
 
 // Load this lane's components of state n (0 -> x0 from LDS).
 template <typename T, class S>
@@ -125,7 +137,7 @@ __device__ __forceinline__ double dn_resid_max(DenseSmem<T, S>& sm, T dt, const 
 // groups of SPP): AT[m] = J(x_{lo+m-1}) transposed, bb[m] = Phi - x_{lo+m}.
 template <typename T, class S>
 __device__ __forceinline__ void dn_elements(DenseSmem<T, S>& sm, T dt, const T* X, int64_t lo, int64_t len,
-                            int64_t m_first, int64_t m_stride, T* AT, T* bb) {
+                            int64_t m_first, int64_t m_stride, T* AT, T* bb, double* hn = nullptr) {
   constexpr int D = S::D, NT = S::NT, NW = NT / PINT_WAVE, SPP = S::SPP, JT = S::JT;
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
   for (int64_t g0 = m_first; g0 < len; g0 += m_stride * SPP) {
@@ -137,10 +149,18 @@ __device__ __forceinline__ void dn_elements(DenseSmem<T, S>& sm, T dt, const T* 
         wave_load<T, S>(X, sm.x0, n - 1, xp, lane);
         wave_load<T, S>(X, sm.x0, n, xc, lane);
         wave_rk4<T, S>(sm.P, dt, xp, phi, &sm.stage[sl], lane);
+        double hm = 0.0;
 #pragma unroll
         for (int r = 0; r < S::R; r++) {
           const int i = lane + 64 * r;
-          if (i < D) bb[m * D + i] = phi[r] - xc[r];
+          if (i < D) {
+            bb[m * D + i] = phi[r] - xc[r];
+            hm = acc_norm(hm, xc[r] - phi[r]);
+          }
+        }
+        if (hn) {  // ||h_n||_inf of the current iterate, as dn_search evaluates it
+          hm = wave_max(hm);
+          if (lane == 0) hn[m] = hm;
         }
       }
     }
@@ -517,14 +537,15 @@ __device__ __forceinline__ void coop_barrier(CoopCtl* c, int G, uint32_t& gen) {
 }
 
 // G workgroups per instance (windowed mode): all of them build the
-// window's elements; workgroup 0 folds the recursion, applies the guarded
-// update and searches the next window.  Two barriers per update.  Needs all
-// workgroups resident at once (cooperative launch).
+// window's elements (speculatively, W + SPEC_SLACK steps from the previous
+// window start, with their residual norms); workgroup 0 picks the window,
+// folds the recursion and applies the guarded update.  Two barriers per
+// update.  Needs all workgroups resident at once (cooperative launch).
 template <typename T, class S>
 __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G, CoopCtl* ctl) {
   constexpr int D = S::D, NT = S::NT;
   __shared__ DenseSmem<T, S> sm;
-  __shared__ int64_t s_win[2];
+  __shared__ int64_t s_win[1];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   T* band_buf = reinterpret_cast<T*>(dyn_lds);  // band_lds_bytes<T, S>() bytes
   __shared__ int32_t s_done;
@@ -546,61 +567,91 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
   if (a.guess == 0)
     for (int64_t idx = (int64_t)g * NT + tid; idx < Tn * D; idx += (int64_t)G * NT) X[idx] = sm.x0[idx % D];
 
-  // workgroup 0 owns the iteration state
+  // workgroup 0 owns the iteration state.  One update: (1) all workgroups
+  // build the elements and residual norms of steps base .. base+Wt-1 of the
+  // current iterate (base = the previous window start: every step before it
+  // is converged and stays untouched); (2) workgroup 0 takes the first
+  // violation p among them (searching further only if there is none), the
+  // window [p, min(T, p+W-1)], folds it and commits the cut update; the next
+  // base is p.  This is the same iteration as searching from the previous
+  // window start after each update, with the search done by the element
+  // pass.
+  const int64_t Wcap = a.Wt;
+  double* hn = reinterpret_cast<double*>(slot + slot_hn_offset<S>(Wcap));
   int64_t k = 0;
   int st = ST_OK;
-  auto decide = [&](int64_t p) {  // search from p, publish the next window
-    double hp;
-    int64_t lo = 0, hi = 0;
-    int done = 0;
-    const int64_t fv = Tn > 0 ? dn_search<T, S>(sm, dt, X, Tn, p, a.tol, &hp) : INT64_MAX;
-    if (fv == INT64_MAX) {
-      st = ST_OK;
-      done = 1;
-    } else if (!(hp < INFINITY)) {
-      st = ST_NONFINITE;
-      done = 1;
-    } else if (k >= a.max_iter) {
-      st = ST_NOT_CONVERGED;
-      done = 1;
-    } else {
-      lo = fv;
-      hi = (W >= Tn - fv + 1) ? Tn : fv + W - 1;
-    }
-    if (tid == 0) {
-      c->lo = lo;
-      c->hi = hi;
-      c->done = done;
-    }
-  };
-
   coop_barrier(c, G, gen);  // initial iterate written everywhere
-  if (g == 0) decide(1);
+  if (g == 0 && tid == 0) {
+    c->lo = 1;
+    c->done = Tn > 0 ? 0 : 1;
+  }
   coop_barrier(c, G, gen);
   for (;;) {
     if (tid == 0) {
       s_win[0] = c->lo;
-      s_win[1] = c->hi;
       s_done = c->done;
     }
     __syncthreads();
     if (s_done) break;
-    const int64_t lo = s_win[0], len = s_win[1] - s_win[0] + 1;
-    dn_elements<T, S>(sm, dt, X, lo, len, g, G, AT, bb);
+    const int64_t base = s_win[0];
+    const int64_t slen = (Tn - base + 1) < Wcap ? (Tn - base + 1) : Wcap;
+    dn_elements<T, S>(sm, dt, X, base, slen, g, G, AT, bb, hn);
     coop_barrier(c, G, gen);
     if (g == 0) {
-      int64_t q;
-      if constexpr (S::BANDED)
-        q = dn_fold_band<T, S>(sm, band_buf, AT, bb, X + (lo - 1) * D, dxb, len, false, a.guard);
-      else
-        q = dn_fold<T, S>(sm, AT, bb, X + (lo - 1) * D, dxb, len, false, a.guard);
-      dn_commit<T, S>(X + (lo - 1) * D, dxb, q);
-      if (q == 0) {
+      // first violation among the evaluated steps
+      int64_t fv = INT64_MAX;
+      for (int64_t m0 = 0; m0 < slen && fv == INT64_MAX; m0 += NT) {
+        const int64_t m = m0 + tid;
+        const int64_t v = (m < slen && !(hn[m] < a.tol)) ? m : INT64_MAX;
+        fv = block_min_i64<NT>(v, sm.redi);
+      }
+      int64_t p = INT64_MAX, next = 0;
+      double hp = 0.0;
+      bool have = true;  // the window's elements are in the slot at offset p - base
+      if (fv != INT64_MAX) {
+        p = base + fv;
+        hp = hn[fv];
+      } else if (base + slen - 1 < Tn) {
+        p = dn_search<T, S>(sm, dt, X, Tn, base + slen, a.tol, &hp);
+        have = false;
+      }
+      int done = 0;
+      if (p == INT64_MAX) {
+        st = ST_OK;
+        done = 1;
+      } else if (!(hp < INFINITY)) {
         st = ST_NONFINITE;
-        if (tid == 0) c->done = 1;
+        done = 1;
+      } else if (k >= a.max_iter) {
+        st = ST_NOT_CONVERGED;
+        done = 1;
       } else {
-        k++;
-        decide(lo);
+        const int64_t hi = (W >= Tn - p + 1) ? Tn : p + W - 1;
+        const int64_t len = hi - p + 1;
+        int64_t off = p - base;
+        if (!have || off + len > slen) {  // beyond the speculative range: build here
+          dn_elements<T, S>(sm, dt, X, p, len, 0, 1, AT, bb);
+          off = 0;
+        }
+        constexpr int64_t ES = S::BANDED ? (int64_t)S::BW * D : (int64_t)D * D;  // scalars per element
+        int64_t q;
+        if constexpr (S::BANDED)
+          q = dn_fold_band<T, S>(sm, band_buf, AT + off * ES, bb + off * D, X + (p - 1) * D, dxb, len, false,
+                                 a.guard);
+        else
+          q = dn_fold<T, S>(sm, AT + off * ES, bb + off * D, X + (p - 1) * D, dxb, len, false, a.guard);
+        dn_commit<T, S>(X + (p - 1) * D, dxb, q);
+        if (q == 0) {
+          st = ST_NONFINITE;
+          done = 1;
+        } else {
+          k++;
+          next = p;
+        }
+      }
+      if (tid == 0) {
+        c->lo = next;
+        c->done = done;
       }
     }
     coop_barrier(c, G, gen);
@@ -779,9 +830,12 @@ static int dense_grid(int64_t B) {
   return (int)(B < cu ? B : cu);
 }
 
+// Elements per workgroup slot: T in plain mode, else the window plus the
+// speculative slack of the cooperative solver (at most T).
 static int64_t dense_Wt(const SolveArgs& a) {
   const int64_t T = a.T_uniform;
-  return (a.window <= 0 || a.window >= T) ? T : a.window;
+  if (a.window <= 0 || a.window >= T) return T;
+  return a.window + SPEC_SLACK < T ? a.window + SPEC_SLACK : T;
 }
 
 // Workgroups per instance for the cooperative solver (windowed mode only):
