@@ -43,10 +43,10 @@ __host__ __device__ constexpr int64_t slot_scalars(int64_t Wt) {
 }
 
 // Speculative slack of the cooperative solver: each update builds the
-// elements of W + SPEC_SLACK steps from the current first violation, so the
-// next first violation (which moves ahead a few steps per update) is read off
+// elements of W + slack steps from the previous window start, so the next
+// first violation (which moves ahead some steps per update) is read off
 // their residuals instead of being searched for separately.
-constexpr int64_t SPEC_SLACK = 32;
+__host__ __device__ constexpr int64_t spec_slack(int64_t W) { return W / 2 > 32 ? W / 2 : 32; }
 
 // Load this lane's components of state n (0 -> x0 from LDS).
 template <typename T, class S>
@@ -545,7 +545,7 @@ template <typename T, class S>
 __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G, CoopCtl* ctl) {
   constexpr int D = S::D, NT = S::NT;
   __shared__ DenseSmem<T, S> sm;
-  __shared__ int64_t s_win[1];
+  __shared__ int64_t s_win[2];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   T* band_buf = reinterpret_cast<T*>(dyn_lds);  // band_lds_bytes<T, S>() bytes
   __shared__ int32_t s_done;
@@ -567,72 +567,111 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
   if (a.guess == 0)
     for (int64_t idx = (int64_t)g * NT + tid; idx < Tn * D; idx += (int64_t)G * NT) X[idx] = sm.x0[idx % D];
 
-  // workgroup 0 owns the iteration state.  One update: (1) all workgroups
-  // build the elements and residual norms of steps base .. base+Wt-1 of the
-  // current iterate (base = the previous window start: every step before it
-  // is converged and stays untouched); (2) workgroup 0 takes the first
-  // violation p among them (searching further only if there is none), the
-  // window [p, min(T, p+W-1)], folds it and commits the cut update; the next
-  // base is p.  This is the same iteration as searching from the previous
-  // window start after each update, with the search done by the element
-  // pass.
+  // workgroup 0 owns the iteration state.  One round: (1) all workgroups
+  // build elements of the current iterate from step `base`; (2) workgroup 0
+  // takes the window [p, min(T, p+W-1)] with p the first violation at or
+  // after base, folds it and commits the cut update.
+  //   Banded (cheap) Jacobians: the round builds W + slack steps from base =
+  // the previous window start, with their residual norms, and p is read off
+  // them (searching further only if there is none); if the window reaches
+  // past the built steps nothing is updated and the next round builds from
+  // p.  Dense Jacobians: workgroup 0 searches p after each update and the
+  // round builds exactly the window.  Both are the iteration that searches
+  // from the previous window start after each update.
+  constexpr bool SPEC = S::BANDED;
   const int64_t Wcap = a.Wt;
   double* hn = reinterpret_cast<double*>(slot + slot_hn_offset<S>(Wcap));
   int64_t k = 0;
   int st = ST_OK;
+  // search from p0 (dense Jacobians): publish the window, or finish
+  auto decide = [&](int64_t p0) {
+    double hp = 0.0;
+    const int64_t p = Tn > 0 ? dn_search<T, S>(sm, dt, X, Tn, p0, a.tol, &hp) : INT64_MAX;
+    int done = 0;
+    int64_t hi = 0;
+    if (p == INT64_MAX) {
+      st = ST_OK;
+      done = 1;
+    } else if (!(hp < INFINITY)) {
+      st = ST_NONFINITE;
+      done = 1;
+    } else if (k >= a.max_iter) {
+      st = ST_NOT_CONVERGED;
+      done = 1;
+    } else {
+      hi = (W >= Tn - p + 1) ? Tn : p + W - 1;
+    }
+    if (tid == 0) {
+      c->lo = done ? 0 : p;
+      c->hi = hi;
+      c->done = done;
+    }
+  };
   coop_barrier(c, G, gen);  // initial iterate written everywhere
-  if (g == 0 && tid == 0) {
-    c->lo = 1;
-    c->done = Tn > 0 ? 0 : 1;
+  if (g == 0) {
+    if constexpr (SPEC) {
+      if (tid == 0) {
+        c->lo = 1;
+        c->done = Tn > 0 ? 0 : 1;
+      }
+    } else {
+      decide(1);
+    }
   }
   coop_barrier(c, G, gen);
   for (;;) {
     if (tid == 0) {
       s_win[0] = c->lo;
+      s_win[1] = c->hi;
       s_done = c->done;
     }
     __syncthreads();
     if (s_done) break;
     const int64_t base = s_win[0];
-    const int64_t slen = (Tn - base + 1) < Wcap ? (Tn - base + 1) : Wcap;
-    dn_elements<T, S>(sm, dt, X, base, slen, g, G, AT, bb, hn);
+    const int64_t slen = SPEC ? ((Tn - base + 1) < Wcap ? (Tn - base + 1) : Wcap) : s_win[1] - base + 1;
+    dn_elements<T, S>(sm, dt, X, base, slen, g, G, AT, bb, SPEC ? hn : nullptr);
     coop_barrier(c, G, gen);
     if (g == 0) {
-      // first violation among the evaluated steps
-      int64_t fv = INT64_MAX;
-      for (int64_t m0 = 0; m0 < slen && fv == INT64_MAX; m0 += NT) {
-        const int64_t m = m0 + tid;
-        const int64_t v = (m < slen && !(hn[m] < a.tol)) ? m : INT64_MAX;
-        fv = block_min_i64<NT>(v, sm.redi);
-      }
-      int64_t p = INT64_MAX, next = 0;
-      double hp = 0.0;
-      bool have = true;  // the window's elements are in the slot at offset p - base
-      if (fv != INT64_MAX) {
-        p = base + fv;
-        hp = hn[fv];
-      } else if (base + slen - 1 < Tn) {
-        p = dn_search<T, S>(sm, dt, X, Tn, base + slen, a.tol, &hp);
-        have = false;
-      }
+      int64_t p = base, next = 0;
       int done = 0;
-      if (p == INT64_MAX) {
-        st = ST_OK;
-        done = 1;
-      } else if (!(hp < INFINITY)) {
-        st = ST_NONFINITE;
-        done = 1;
-      } else if (k >= a.max_iter) {
-        st = ST_NOT_CONVERGED;
-        done = 1;
-      } else {
-        const int64_t hi = (W >= Tn - p + 1) ? Tn : p + W - 1;
-        const int64_t len = hi - p + 1;
-        int64_t off = p - base;
-        if (!have || off + len > slen) {  // beyond the speculative range: build here
-          dn_elements<T, S>(sm, dt, X, p, len, 0, 1, AT, bb);
-          off = 0;
+      bool fold = true;
+      if constexpr (SPEC) {
+        // first violation among the built steps
+        int64_t fv = INT64_MAX;
+        for (int64_t m0 = 0; m0 < slen && fv == INT64_MAX; m0 += NT) {
+          const int64_t m = m0 + tid;
+          const int64_t v = (m < slen && !(hn[m] < a.tol)) ? m : INT64_MAX;
+          fv = block_min_i64<NT>(v, sm.redi);
         }
+        double hp = 0.0;
+        bool have = true;  // the window's elements are in the slot at offset p - base
+        p = INT64_MAX;
+        if (fv != INT64_MAX) {
+          p = base + fv;
+          hp = hn[fv];
+        } else if (base + slen - 1 < Tn) {
+          p = dn_search<T, S>(sm, dt, X, Tn, base + slen, a.tol, &hp);
+          have = false;
+        }
+        if (p == INT64_MAX) {
+          st = ST_OK;
+          done = 1;
+        } else if (!(hp < INFINITY)) {
+          st = ST_NONFINITE;
+          done = 1;
+        } else if (k >= a.max_iter) {
+          st = ST_NOT_CONVERGED;
+          done = 1;
+        } else {
+          const int64_t len = ((W >= Tn - p + 1) ? Tn : p + W - 1) - p + 1;
+          fold = have && (p - base) + len <= slen;  // else rebuild from p
+          next = p;
+        }
+        if (done) fold = false;
+      }
+      if (fold) {
+        const int64_t len = ((W >= Tn - p + 1) ? Tn : p + W - 1) - p + 1;
+        const int64_t off = p - base;
         constexpr int64_t ES = S::BANDED ? (int64_t)S::BW * D : (int64_t)D * D;  // scalars per element
         int64_t q;
         if constexpr (S::BANDED)
@@ -646,12 +685,19 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
           done = 1;
         } else {
           k++;
-          next = p;
         }
       }
-      if (tid == 0) {
-        c->lo = next;
-        c->done = done;
+      if constexpr (SPEC) {
+        if (tid == 0) {
+          c->lo = next;
+          c->done = done;
+        }
+      } else {
+        if (done) {
+          if (tid == 0) c->done = 1;
+        } else {
+          decide(p);
+        }
       }
     }
     coop_barrier(c, G, gen);
@@ -830,12 +876,14 @@ static int dense_grid(int64_t B) {
   return (int)(B < cu ? B : cu);
 }
 
-// Elements per workgroup slot: T in plain mode, else the window plus the
-// speculative slack of the cooperative solver (at most T).
+// Elements per workgroup slot: T in plain mode, else the window (plus the
+// speculative slack of the cooperative solver for banded Jacobians), at most T.
+template <class S>
 static int64_t dense_Wt(const SolveArgs& a) {
   const int64_t T = a.T_uniform;
   if (a.window <= 0 || a.window >= T) return T;
-  return a.window + SPEC_SLACK < T ? a.window + SPEC_SLACK : T;
+  const int64_t w = a.window + (S::BANDED ? spec_slack(a.window) : 0);
+  return w < T ? w : T;
 }
 
 // Workgroups per instance for the cooperative solver (windowed mode only):
@@ -844,7 +892,7 @@ static int64_t dense_Wt(const SolveArgs& a) {
 template <typename T, class S>
 static int coop_groups(const SolveArgs& a) {
   if (a.window <= 0 || a.B <= 0 || a.T_uniform <= 0) return 1;
-  const int64_t W = dense_Wt(a);
+  const int64_t W = dense_Wt<S>(a);
   int64_t G = (W + S::SPP - 1) / S::SPP;
   if (G > 64) G = 64;
   int per_cu = 0;
@@ -864,7 +912,7 @@ struct DenseWs {
 template <typename T, class S>
 static DenseWs dense_ws_layout(const SolveArgs& a) {
   DenseWs l{};
-  const int64_t Wt = dense_Wt(a) > 0 ? dense_Wt(a) : 1;
+  const int64_t Wt = dense_Wt<S>(a) > 0 ? dense_Wt<S>(a) : 1;
   const int64_t B = a.B > 0 ? a.B : 1;
   l.per_slot = align_up((size_t)slot_scalars<S>(Wt) * sizeof(T));
   l.nslots = B > dense_grid(B) ? B : dense_grid(B);
@@ -895,7 +943,7 @@ int dense_solve(const SolveArgs& a) {
     DenseKArgs k = to_dk(a);
     k.queue = reinterpret_cast<uint32_t*>(w);
     k.ws_elems = w + l.slots_off;
-    k.Wt = dense_Wt(a);
+    k.Wt = dense_Wt<S>(a);
     k.slot_stride = (int64_t)(l.per_slot / sizeof(T));
     CoopCtl* ctl = reinterpret_cast<CoopCtl*>(w + l.ctl_off);
     // queue counter and control blocks start at zero (a kernel, not a memset)
