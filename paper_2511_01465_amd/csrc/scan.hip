@@ -387,19 +387,27 @@ struct Mfma<float> {  // v_mfma_f32_16x16x4f32: acc (lane l, reg r) = (4(l/16) +
   __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
 };
 
-template <int D>
+// STAT ("stationary product", FP64 with D a multiple of 64): the running
+// product stays in the MFMA accumulators, each wave owning NTL/4 column tiles
+// -- the FP64 16x16x4 accumulator layout (lane l, reg r) = (l/16 + 4r, l%16)
+// is exactly the B-operand layout of the next product's k-steps -- and only
+// the element being folded passes through LDS (rows padded to DP + 4).
+// Otherwise the product lives in LDS and the element is read from HBM.
+template <typename T, int D>
 struct DenseScanShape {
   static constexpr int DP = (D + 15) / 16 * 16;    // padded to MFMA tiles
   static constexpr int NTL = DP / 16;               // 16x16 tiles per dimension
-  static constexpr int PS = (DP % 32 == 0) ? DP + 16 : DP;  // LDS row stride
   static constexpr int NT = 256, NW = 4;
+  static constexpr bool STAT = sizeof(T) == 8 && D % 64 == 0;
+  static constexpr int CT = NTL / NW;               // STAT: column tiles per wave
+  static constexpr int PS = STAT ? DP + 4 : ((DP % 32 == 0) ? DP + 16 : DP);  // LDS row stride
   static constexpr int RT = (NTL + NW - 1) / NW;   // row tiles per wave
 };
 
 template <typename T, int D>
 constexpr size_t dense_scan_lds() {
-  using SH = DenseScanShape<D>;
-  return (size_t)SH::DP * SH::PS * sizeof(T) + 4 * (size_t)SH::DP * sizeof(T);
+  using SH = DenseScanShape<T, D>;
+  return (size_t)SH::DP * SH::PS * sizeof(T) + 5 * (size_t)SH::DP * sizeof(T);
 }
 
 // z <- M z + c for a D x D row-major M in global memory, by the whole block;
@@ -425,7 +433,7 @@ __device__ __forceinline__ void block_matvec_g(const T* M, const T* c, T* z, T* 
 
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
-  using SH = DenseScanShape<D>;
+  using SH = DenseScanShape<T, D>;
   using MF = Mfma<T>;
   constexpr int DP = SH::DP, NTL = SH::NTL, PS = SH::PS, NT = SH::NT, RT = SH::RT;
   constexpr int E = D * D + D;
@@ -434,6 +442,7 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
   T* sq = sP + DP * PS;                             // running b-part
   T* sz = sq + DP;                                  // z vector
   T* st = sz + DP;                                  // scratch vector
+  T* sq2 = st + DP;                                 // STAT: second b-part buffer
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
   if (tid == 0) s_tile = atomicAdd(a.counter, 1u);
@@ -446,13 +455,93 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
   const T* Aseq = static_cast<const T*>(a.A) + (seq * a.N + e0) * D * D;
   const T* bseq = static_cast<const T*>(a.b) + (seq * a.N + e0) * D;
 
-  // P <- A_0 (zero padded), q <- b_0
-  for (int idx = tid; idx < DP * DP; idx += NT) {
-    const int i = idx / DP, j = idx % DP;
-    sP[i * PS + j] = (i < D && j < D) ? Aseq[i * D + j] : T(0);
-  }
-  for (int i = tid; i < DP; i += NT) sq[i] = i < D ? bseq[i] : T(0);
-  __syncthreads();
+  if constexpr (SH::STAT) {
+    // ---- stationary product: P in accumulators, A_m staged through LDS ----
+    static_assert(D == DP && (DP * DP) % (2 * NT) == 0, "stationary shape");
+    constexpr int CT = SH::CT, NPF = DP * DP / (2 * NT);  // double2 loads per thread per element
+    typedef double v2_t __attribute__((ext_vector_type(2)));
+    const int col0 = wv * CT;
+    pint_d4 P[NTL][CT];
+#pragma unroll
+    for (int it = 0; it < NTL; it++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          P[it][ct][r] = Aseq[(16 * it + lane / 16 + 4 * r) * D + 16 * (col0 + ct) + lane % 16];
+    for (int i = tid; i < DP; i += NT) sq[i] = bseq[i];
+    v2_t pf[NPF];
+    auto prefetch = [&](int m) {
+      const v2_t* src = reinterpret_cast<const v2_t*>(Aseq + (int64_t)m * D * D);
+#pragma unroll
+      for (int j = 0; j < NPF; j++) pf[j] = src[j * NT + tid];
+    };
+    if (n_el > 1) prefetch(1);
+    for (int m = 1; m < n_el; m++) {
+      const T* qo = (m & 1) ? sq : sq2;  // b-part after element m-1
+      T* qn = (m & 1) ? sq2 : sq;        // after element m
+      __syncthreads();  // A_{m-1} and the old b-part no longer read
+#pragma unroll
+      for (int j = 0; j < NPF; j++) {
+        const int q = 2 * (j * NT + tid), i = q / D, k = q % D;
+        sP[i * PS + k] = pf[j][0];
+        sP[i * PS + k + 1] = pf[j][1];
+      }
+      __syncthreads();  // A_m staged
+      if (m + 1 < n_el) prefetch(m + 1);  // lands while the products run
+      {  // b-part: A_m q + b_m
+        constexpr int QC = 2;
+        const int i = tid / QC, h = tid % QC;
+        T part = T(0);
+        if (i < D)
+#pragma unroll 8
+          for (int k = 0; k < D / QC; k++) part += sP[i * PS + h * (D / QC) + k] * qo[h * (D / QC) + k];
+        part += __shfl_xor(part, 1, PINT_WAVE);
+        if (i < D && h == 0) qn[i] = part + bseq[(int64_t)m * D + i];
+      }
+      pint_d4 Pn[NTL][CT];
+#pragma unroll
+      for (int it = 0; it < NTL; it++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) Pn[it][ct] = pint_d4{};
+#pragma unroll
+      for (int kt = 0; kt < NTL; kt++) {
+#pragma unroll
+        for (int qk = 0; qk < 4; qk++) {
+#pragma unroll
+          for (int it = 0; it < NTL; it++) {
+            const double av = sP[(16 * it + lane % 16) * PS + 16 * kt + 4 * qk + lane / 16];
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++)
+              Pn[it][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, P[kt][ct][qk], Pn[it][ct], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < NTL; it++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) P[it][ct] = Pn[it][ct];
+    }
+    // the tile's product into LDS (row stride PS) for the rest of the kernel
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NTL; it++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          sP[(16 * it + lane / 16 + 4 * r) * PS + 16 * (col0 + ct) + lane % 16] = P[it][ct][r];
+    if ((n_el & 1) == 0)  // the final b-part is in sq2
+      for (int i = tid; i < DP; i += NT) sq[i] = sq2[i];
+    __syncthreads();
+  } else {
+    // P <- A_0 (zero padded), q <- b_0
+    for (int idx = tid; idx < DP * DP; idx += NT) {
+      const int i = idx / DP, j = idx % DP;
+      sP[i * PS + j] = (i < D && j < D) ? Aseq[i * D + j] : T(0);
+    }
+    for (int i = tid; i < DP; i += NT) sq[i] = i < D ? bseq[i] : T(0);
+    __syncthreads();
 
   // fold the remaining elements: (P, q) <- (A_m P, A_m q + b_m)
   for (int m = 1; m < n_el; m++) {
@@ -504,6 +593,7 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
     if (tid < D) sq[tid] = st[tid];
     __syncthreads();
   }
+  }  // generic fold
 
   // lookback for z at the start of the tile
   const int64_t base = seq * a.tiles_per_seq;
@@ -555,11 +645,43 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
     if (tid == 0) publish_flag(flags + ts, FLAG_INCL);
   }
 
-  // outputs: z_{e0+m+1} = A_m z + b_m in order
+  // outputs: z_{e0+m+1} = A_m z + b_m in order.  QC threads per row; each
+  // thread's row segment of A_{m+1} and b_{m+1} are loaded during element m
+  // (the barriers order LDS only, so those loads stay in flight).
   T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
-  for (int m = 0; m < n_el; m++) {
-    block_matvec_g<T, D, NT>(Aseq + (int64_t)m * D * D, bseq + (int64_t)m * D, sz, st, false);
-    for (int i = tid; i < D; i += NT) zg[(int64_t)m * D + i] = sz[i];
+  {
+    constexpr int QC = (D * 2 <= NT) ? ((D * 4 <= NT) ? 4 : 2) : 1, SEG = D / QC;
+    static_assert(D % QC == 0, "row split");
+    const int i = tid / QC, h = tid % QC;
+    const bool act = i < D;
+    const int ii = act ? i : 0;
+    T cur[SEG], nxt[SEG], bc = T(0), bn = T(0);
+#pragma unroll
+    for (int k = 0; k < SEG; k++) cur[k] = Aseq[(int64_t)ii * D + h * SEG + k];
+    bc = bseq[ii];
+    for (int m = 0; m < n_el; m++) {
+      if (m + 1 < n_el) {
+        const T* An = Aseq + (int64_t)(m + 1) * D * D + (int64_t)ii * D + h * SEG;
+#pragma unroll
+        for (int k = 0; k < SEG; k++) nxt[k] = An[k];
+        bn = bseq[(int64_t)(m + 1) * D + ii];
+      }
+      T part = T(0);
+#pragma unroll
+      for (int k = 0; k < SEG; k++) part += cur[k] * sz[h * SEG + k];
+#pragma unroll
+      for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
+      if (act && h == 0) st[i] = part + bc;
+      lds_barrier();
+      if (tid < D) {
+        sz[tid] = st[tid];
+        zg[(int64_t)m * D + tid] = st[tid];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int k = 0; k < SEG; k++) cur[k] = nxt[k];
+      bc = bn;
+    }
   }
 }
 
