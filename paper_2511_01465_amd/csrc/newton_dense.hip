@@ -386,6 +386,10 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
           if (i >= D - BOFF) zx[i + BOFF - D] = z;
           if (i + BOFF + D < D + BW - 1) zx[i + BOFF + D] = z;
         }
+        // other lanes read these next step; within one thread those addresses
+        // need not alias, so keep the compiler from moving reads above them
+        // (the hardware completes one wave's LDS operations in order)
+        asm volatile("" ::: "memory");
         const T xn = L[CH * NB + CH * D + m * D + i] + z;
         if (lane < D) {
           xnb[(c0 + m) * D + i] = xn;

@@ -363,6 +363,256 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
   stage_out<T, RB, SH::VB, NT>(zg, sb, n_el * D, tid);
 }
 
+// ------------------------------------------------------- d = 5 .. 8 ------
+
+// One wave per workgroup, a run of S consecutive elements per lane.  An 8x8 affine map and a
+// composition partner do not both fit a lane's registers alongside a
+// shuffled copy, so the in-wave scan and the lookback reduction pass maps
+// through LDS and stream the partner's rows while composing.  Every hand-off
+// through LDS between lanes is separated by a workgroup barrier: within one
+// thread the reads of a partner's map and the writes of its own never alias,
+// so nothing else would keep the compiler from reordering them.
+// Elements are read straight from global memory (a row at a time while
+// folding) and read again, from cache, for the outputs; LDS holds only the
+// scan and a 16-map lookback buffer.
+template <int D, typename T>
+struct WideShape {
+  static constexpr int NT = 64, E = D * D + D, EP = E + 1, LW = 16;  // LW: lookback maps per pass
+  static constexpr int S = 64, TILE = NT * S;  // S consecutive elements per lane
+  static constexpr size_t OFF_Y = (size_t)NT * EP;
+  static constexpr size_t OFF_ACC = OFF_Y + (size_t)LW * EP;
+  static constexpr size_t OFF_T = OFF_ACC + EP;
+  static constexpr size_t OFF_Z = OFF_T + EP;
+  static constexpr size_t LDS = (OFF_Z + 2 * D) * sizeof(T);
+};
+
+// l <- l o P (P applied first); P in LDS as A row-major then b.
+template <typename T, int D>
+__device__ __forceinline__ void aff_after_lds(Aff<T, D>& l, const T* P) {
+  Aff<T, D> r;
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+#pragma unroll
+    for (int j = 0; j < D; j++) r.A[i * D + j] = T(0);
+    r.b[i] = l.b[i];
+  }
+#pragma unroll
+  for (int k = 0; k < D; k++) {
+    T prow[D + 1];
+#pragma unroll
+    for (int j = 0; j < D; j++) prow[j] = P[k * D + j];
+    prow[D] = P[D * D + k];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      const T lik = l.A[i * D + k];
+#pragma unroll
+      for (int j = 0; j < D; j++) r.A[i * D + j] += lik * prow[j];
+      r.b[i] += lik * prow[D];
+    }
+  }
+  l = r;
+}
+
+// l <- E o l (E applied last), E read row by row from global memory.
+template <typename T, int D>
+__device__ __forceinline__ void aff_before_g(Aff<T, D>& l, const T* EA, const T* Eb) {
+  Aff<T, D> r;
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    T er[D];
+#pragma unroll
+    for (int k = 0; k < D; k++) er[k] = EA[i * D + k];
+    T bi = Eb[i];
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+      T t = T(0);
+#pragma unroll
+      for (int k = 0; k < D; k++) t += er[k] * l.A[k * D + j];
+      r.A[i * D + j] = t;
+    }
+#pragma unroll
+    for (int k = 0; k < D; k++) bi += er[k] * l.b[k];
+    r.b[i] = bi;
+  }
+  l = r;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void aff_store_lds(T* p, const Aff<T, D>& e) {
+#pragma unroll
+  for (int i = 0; i < D * D; i++) p[i] = e.A[i];
+#pragma unroll
+  for (int i = 0; i < D; i++) p[D * D + i] = e.b[i];
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void aff_load_lds(Aff<T, D>& e, const T* p) {
+#pragma unroll
+  for (int i = 0; i < D * D; i++) e.A[i] = p[i];
+#pragma unroll
+  for (int i = 0; i < D; i++) e.b[i] = p[D * D + i];
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void aff_identity_lds(T* p) {
+#pragma unroll
+  for (int i = 0; i < D * D; i++) p[i] = (i / D == i % D) ? T(1) : T(0);
+#pragma unroll
+  for (int i = 0; i < D; i++) p[D * D + i] = T(0);
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(64) void k_scan_wide(ScanArgs a) {
+  using SH = WideShape<D, T>;
+  constexpr int NT = SH::NT, S = SH::S, TILE = SH::TILE, E = SH::E, EP = SH::EP, LW = SH::LW;
+  extern __shared__ __align__(16) unsigned char wide_lds[];
+  T* L = reinterpret_cast<T*>(wide_lds);
+  T* sX = L;                // [NT][EP]: inclusive prefixes of the tile
+  T* sY = L + SH::OFF_Y;    // [LW][EP]: lookback maps
+  T* sAcc = L + SH::OFF_ACC;
+  T* sT = L + SH::OFF_T;    // the tile's aggregate
+  T* sZ = L + SH::OFF_Z;    // z_in (D), then the inclusive vector found (D)
+  __shared__ uint32_t s_tile;
+  const int lane = threadIdx.x;
+  if (lane == 0) s_tile = atomicAdd(a.counter, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t seq = tile / a.tiles_per_seq, ts = tile % a.tiles_per_seq;
+  const int64_t e0 = ts * TILE;
+  const int n_el = (int)((a.N - e0) < TILE ? (a.N - e0) : TILE);
+  const int my_n = n_el - lane * S < 0 ? 0 : (n_el - lane * S < S ? n_el - lane * S : S);  // elements of this lane
+  const int64_t el = seq * a.N + e0 + (int64_t)lane * S;
+  const T* Ae = static_cast<const T*>(a.A) + el * D * D;
+  const T* be = static_cast<const T*>(a.b) + el * D;
+
+  Aff<T, D> agg;
+  aff_identity(agg);
+  for (int s = 0; s < my_n; s++) aff_before_g<T, D>(agg, Ae + (int64_t)s * D * D, be + (int64_t)s * D);
+  // inclusive scan over the lanes (Hillis-Steele, partners read from LDS;
+  // every lane's reads of a level precede its writes)
+  aff_store_lds<T, D>(sX + lane * EP, agg);
+  __syncthreads();
+#pragma unroll
+  for (int o = 1; o < NT; o <<= 1) {
+    if (lane >= o) aff_after_lds<T, D>(agg, sX + (lane - o) * EP);
+    __syncthreads();  // every lane has read the previous level
+    aff_store_lds<T, D>(sX + lane * EP, agg);
+    __syncthreads();
+  }
+  if (lane == NT - 1) aff_store_lds<T, D>(sT, agg);
+  __syncthreads();
+
+  const int64_t base = seq * a.tiles_per_seq;
+  uint32_t* flags = a.flags + base;
+  T* aggp = static_cast<T*>(a.agg) + base * E;
+  T* inclp = static_cast<T*>(a.incl) + base * D;
+  if (ts == 0) {
+    if (lane < D) sZ[lane] = a.z0 ? static_cast<const T*>(a.z0)[seq * D + lane] : T(0);
+  } else {
+    for (int i = lane; i < E; i += NT) st_payload(aggp + ts * E + i, sT[i]);
+    if (lane == 0) {
+      publish_flag(flags + ts, FLAG_AGG);
+      aff_identity_lds<T, D>(sAcc);
+    }
+    __syncthreads();
+    int64_t end = ts - 1;
+    for (;;) {
+      uint32_t f;
+      const int k = lookback_window(flags, end, a.err, f);
+      // aggregates end, end-1, ..., end-k+1, LW at a time (newest first):
+      // acc <- acc o (m_0 o m_1 o ... o m_{n-1})
+      for (int c0 = 0; c0 < k; c0 += LW) {
+        const int n = (k - c0) < LW ? (k - c0) : LW;
+        if (lane < LW) {
+          T* my = sY + lane * EP;
+          if (lane < n) {
+            const T* src = aggp + (end - c0 - lane) * E;
+            for (int i = 0; i < E; i++) my[i] = ld_payload(src + i);
+          } else {
+            aff_identity_lds<T, D>(my);
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int off = 1; off < LW; off <<= 1) {
+          // lane reads lane+off (not written at this level) and writes itself
+          if (lane < LW && (lane & (2 * off - 1)) == 0) {
+            Aff<T, D> v;
+            aff_load_lds<T, D>(v, sY + lane * EP);
+            aff_after_lds<T, D>(v, sY + (lane + off) * EP);
+            aff_store_lds<T, D>(sY + lane * EP, v);
+          }
+          __syncthreads();
+        }
+        if (lane == 0) {
+          Aff<T, D> v;
+          aff_load_lds<T, D>(v, sAcc);
+          aff_after_lds<T, D>(v, sY);
+          aff_store_lds<T, D>(sAcc, v);
+        }
+        __syncthreads();  // sY is rewritten by the next pass; sAcc read below
+      }
+      if (k < PINT_WAVE) {
+        const int64_t j = end - k;  // the inclusive predecessor
+        if (lane < D) sZ[D + lane] = j >= 0 ? ld_payload(inclp + j * D + lane) : T(0);
+        __syncthreads();
+        if (lane < D) {
+          T t = sAcc[D * D + lane];
+#pragma unroll
+          for (int q = 0; q < D; q++) t += sAcc[lane * D + q] * sZ[D + q];
+          sZ[lane] = t;
+        }
+        break;
+      }
+      end -= PINT_WAVE;
+    }
+  }
+  __syncthreads();  // z_in in sZ
+  // this tile's inclusive vector
+  if (lane < D) {
+    T t = sT[D * D + lane];
+#pragma unroll
+    for (int q = 0; q < D; q++) t += sT[lane * D + q] * sZ[q];
+    st_payload(inclp + ts * D + lane, t);
+  }
+  if (lane == 0) publish_flag(flags + ts, FLAG_INCL);
+
+  // outputs of this lane's run, from z at its start (the previous lane's
+  // inclusive prefix applied to z_in)
+  if (my_n > 0) {
+    T z[D];
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < D; i++) z[i] = sZ[i];
+    } else {
+      const T* P = sX + (lane - 1) * EP;
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        T t = P[D * D + i];
+#pragma unroll
+        for (int q = 0; q < D; q++) t += P[i * D + q] * sZ[q];
+        z[i] = t;
+      }
+    }
+    T* zg = static_cast<T*>(a.z) + el * D;
+    for (int s = 0; s < my_n; s++) {
+      T t[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        T acc = be[(int64_t)s * D + i];
+#pragma unroll
+        for (int q = 0; q < D; q++) acc += Ae[(int64_t)s * D * D + i * D + q] * z[q];
+        t[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        z[i] = t[i];
+        zg[(int64_t)s * D + i] = t[i];
+      }
+    }
+  }
+}
+
 // ----------------------------------------------------------- dense d ------
 
 typedef double pint_d4 __attribute__((ext_vector_type(4)));
@@ -692,8 +942,8 @@ static int scan_tile_elems(int d, int dtype, int tile) {
     switch (d) {
 #define PINT_SMALL_TILE(DD)                                                               \
   case DD:                                                                                \
-    return dtype == 0 ? SmallShape<DD, double>::TILE                    \
-                      : SmallShape<DD, float>::TILE;
+    return dtype == 0 ? (DD >= 5 ? WideShape<DD, double>::TILE : SmallShape<DD, double>::TILE) \
+                      : (DD >= 5 ? WideShape<DD, float>::TILE : SmallShape<DD, float>::TILE);
       PINT_SMALL_TILE(1) PINT_SMALL_TILE(2) PINT_SMALL_TILE(3) PINT_SMALL_TILE(4)
       PINT_SMALL_TILE(5) PINT_SMALL_TILE(6) PINT_SMALL_TILE(7) PINT_SMALL_TILE(8)
 #undef PINT_SMALL_TILE
@@ -733,7 +983,19 @@ size_t scan_ws_bytes(int d, int64_t B, int64_t N, int tile, int dtype) {
 
 template <typename T, int D>
 static int launch_small(const ScanArgs& sa, int64_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_scan_small<T, D>), dim3((unsigned)grid), dim3(SmallShape<D, T>::NT), 0, s, sa);
+  if constexpr (D >= 5) {
+    constexpr size_t lds = WideShape<D, T>::LDS;
+    static bool attr_set = false;
+    if (!attr_set) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_wide<T, D>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return ST_DEVICE;
+      attr_set = true;
+    }
+    hipLaunchKernelGGL((k_scan_wide<T, D>), dim3((unsigned)grid), dim3(64), lds, s, sa);
+  } else {
+    hipLaunchKernelGGL((k_scan_small<T, D>), dim3((unsigned)grid), dim3(SmallShape<D, T>::NT), 0, s, sa);
+  }
   return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
 }
 

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 # elements per tile of the small-d kernel (FP64): 256 threads x S elements
-SMALL_TILE = {1: 3072, 2: 1024, 3: 512, 4: 256, 8: 64}
+SMALL_TILE = {1: 3072, 2: 1024, 3: 512, 4: 256, 5: 4096, 6: 4096, 7: 4096, 8: 4096}
 
 
 def _ref(orc, A, b, z0):
@@ -42,7 +42,7 @@ def _check(pint, orc, d, N, B, dtype, with_z0, seed, tile=0):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("d", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_small_d_several_tiles_ragged(pint, orc, d, dtype):
     tile = SMALL_TILE[d] if dtype == "f64" else None
     N = 3 * (tile or SMALL_TILE[d]) + 17
@@ -69,7 +69,7 @@ def test_dense_tile_sizes(pint, orc):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("d", [1, 2, 3, 4])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 8])
 def test_many_tiles_mixed(pint, orc, d, dtype):
     """Several times more tiles than workgroups resident on the device, three
     sequences of odd length so that later sequences start misaligned for
