@@ -20,8 +20,10 @@
 // Waits are bounded so every wave exits even if a predecessor never
 // publishes.
 //
-//   small d (<= 8): tiles staged through LDS, each thread folds a run of
-//     elements, wave shuffles + LDS scan the thread aggregates;
+//   d <= 3: tiles staged through LDS, each thread folds a run of elements,
+//     wave shuffles + LDS scan the thread aggregates;
+//   d = 4..8: one wave per tile, each lane folds a run of 64 elements read
+//     from global memory, scan and lookback through LDS;
 //   dense d (16..128): each tile folds its elements with MFMA matrix
 //     products (FP64 16x16x4 or FP32 16x16x4), the running product in LDS.
 #include "internal.h"
@@ -363,7 +365,7 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
   stage_out<T, RB, SH::VB, NT>(zg, sb, n_el * D, tid);
 }
 
-// ------------------------------------------------------- d = 5 .. 8 ------
+// ------------------------------------------------------- d = 4 .. 8 ------
 
 // One wave per workgroup, a run of S consecutive elements per lane.  An 8x8 affine map and a
 // composition partner do not both fit a lane's registers alongside a
@@ -942,8 +944,8 @@ static int scan_tile_elems(int d, int dtype, int tile) {
     switch (d) {
 #define PINT_SMALL_TILE(DD)                                                               \
   case DD:                                                                                \
-    return dtype == 0 ? (DD >= 5 ? WideShape<DD, double>::TILE : SmallShape<DD, double>::TILE) \
-                      : (DD >= 5 ? WideShape<DD, float>::TILE : SmallShape<DD, float>::TILE);
+    return dtype == 0 ? (DD >= 4 ? WideShape<DD, double>::TILE : SmallShape<DD, double>::TILE) \
+                      : (DD >= 4 ? WideShape<DD, float>::TILE : SmallShape<DD, float>::TILE);
       PINT_SMALL_TILE(1) PINT_SMALL_TILE(2) PINT_SMALL_TILE(3) PINT_SMALL_TILE(4)
       PINT_SMALL_TILE(5) PINT_SMALL_TILE(6) PINT_SMALL_TILE(7) PINT_SMALL_TILE(8)
 #undef PINT_SMALL_TILE
@@ -983,7 +985,7 @@ size_t scan_ws_bytes(int d, int64_t B, int64_t N, int tile, int dtype) {
 
 template <typename T, int D>
 static int launch_small(const ScanArgs& sa, int64_t grid, hipStream_t s) {
-  if constexpr (D >= 5) {
+  if constexpr (D >= 4) {
     constexpr size_t lds = WideShape<D, T>::LDS;
     static bool attr_set = false;
     if (!attr_set) {

@@ -12,8 +12,9 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
-# elements per tile of the small-d kernel (FP64): 256 threads x S elements
-SMALL_TILE = {1: 3072, 2: 1024, 3: 512, 4: 256, 5: 4096, 6: 4096, 7: 4096, 8: 4096}
+# elements per tile of the small-d kernels (FP64): 256 threads x S elements for
+# d <= 3, 64 lanes x 64 elements for d >= 4
+SMALL_TILE = {1: 3072, 2: 1024, 3: 512, 4: 4096, 5: 4096, 6: 4096, 7: 4096, 8: 4096}
 
 
 def _ref(orc, A, b, z0):
