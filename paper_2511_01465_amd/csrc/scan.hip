@@ -116,7 +116,9 @@ struct SmallShape {
   static constexpr int E = D * D + D;
   static constexpr int S0 = 49152 / (E * (int)sizeof(T) * NT);
   static constexpr int S = S0 < 1 ? 1 : (S0 > 16 ? 16 : S0);
-  static constexpr int TILE = NT * S;
+  static constexpr int CH = NT * S;   // elements per chunk (one LDS staging)
+  static constexpr int C = 8;         // chunks per tile (one lookback per tile)
+  static constexpr int TILE = CH * C;
   static constexpr int RA = S * D * D, RB = S * D;
   static constexpr int VA = vec_width<T>(RA), VB = vec_width<T>(RB);
 };
@@ -185,10 +187,15 @@ __device__ __forceinline__ void stage_out(T* __restrict__ g, const T* lds, int n
   }
 }
 
+// A tile is C chunks of NT*S elements.  Pass 1 stages the chunks in turn
+// and composes their aggregates into the tile's; after the lookback, pass 2
+// stages them again (the second read mostly hits the last-level cache) and
+// writes the outputs with z carried from chunk to chunk.  One lookback per
+// C chunks: the lookback's latency, not bandwidth, bounds the scan.
 template <typename T, int D>
 __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs a) {
   using SH = SmallShape<D, T>;
-  constexpr int NT = SH::NT, S = SH::S, TILE = SH::TILE, NW = NT / PINT_WAVE, E = SH::E;
+  constexpr int NT = SH::NT, S = SH::S, CH = SH::CH, TILE = SH::TILE, NW = NT / PINT_WAVE, E = SH::E;
   constexpr int RA = SH::RA, RB = SH::RB, PA = RA + 1, PB = RB + 1;
   __shared__ T sA[NT * PA];
   __shared__ T sb[NT * PB];
@@ -197,38 +204,59 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
   __shared__ T s_zin[D], s_wz[NW][D];
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
-  if (tid == 0) s_tile = atomicAdd(a.counter, 1u);
+  if (tid == 0) {
+    s_tile = atomicAdd(a.counter, 1u);
+    aff_identity(s_tagg);
+  }
   __syncthreads();
   const int64_t tile = s_tile;
   const int64_t seq = tile / a.tiles_per_seq, ts = tile % a.tiles_per_seq;
   const int64_t e0 = ts * TILE;
   const int n_el = (int)((a.N - e0) < TILE ? (a.N - e0) : TILE);
+  const int nch = (n_el + CH - 1) / CH;
   const T* Ag = static_cast<const T*>(a.A) + (seq * a.N + e0) * D * D;
   const T* bg = static_cast<const T*>(a.b) + (seq * a.N + e0) * D;
-  stage_in<T, RA, SH::VA, NT>(Ag, sA, n_el * D * D, tid);
-  stage_in<T, RB, SH::VB, NT>(bg, sb, n_el * D, tid);
-  __syncthreads();
-
-  // each thread folds its S consecutive elements into one map
   const T* myA = sA + tid * PA;
   const T* myb = sb + tid * PB;
-  Aff<T, D> agg;
-  aff_identity(agg);
-#pragma unroll
-  for (int s = 0; s < S; s++) {
-    if (tid * S + s < n_el) {
-      Aff<T, D> e;
-#pragma unroll
-      for (int i = 0; i < D * D; i++) e.A[i] = myA[s * D * D + i];
-#pragma unroll
-      for (int i = 0; i < D; i++) e.b[i] = myb[s * D + i];
-      aff_after(e, agg);
-      agg = e;
+
+  // chunk c into LDS; each thread folds its S elements; block scan:
+  // agg = composition of threads 0..tid of the chunk
+  auto chunk_scan = [&](int c, bool load, Aff<T, D>& agg, int& cn) {
+    const int c0 = c * CH;
+    cn = (n_el - c0) < CH ? (n_el - c0) : CH;
+    if (load) {
+      stage_in<T, RA, SH::VA, NT>(Ag + (int64_t)c0 * D * D, sA, cn * D * D, tid);
+      stage_in<T, RB, SH::VB, NT>(bg + (int64_t)c0 * D, sb, cn * D, tid);
+      __syncthreads();
     }
+    aff_identity(agg);
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+      if (tid * S + s < cn) {
+        Aff<T, D> e;
+#pragma unroll
+        for (int i = 0; i < D * D; i++) e.A[i] = myA[s * D * D + i];
+#pragma unroll
+        for (int i = 0; i < D; i++) e.b[i] = myb[s * D + i];
+        aff_after(e, agg);
+        agg = e;
+      }
+    }
+    block_scan_aff<T, D, NT>(agg, s_aff);
+  };
+
+  // pass 1: the tile's aggregate
+  Aff<T, D> agg;
+  int cn = 0;
+  for (int c = 0; c < nch; c++) {
+    chunk_scan(c, true, agg, cn);
+    if (tid == NT - 1) {
+      Aff<T, D> t = agg;
+      aff_after(t, s_tagg);  // this chunk after the earlier ones
+      s_tagg = t;
+    }
+    __syncthreads();  // s_tagg updated; the chunk's LDS may be rewritten
   }
-  block_scan_aff<T, D, NT>(agg, s_aff);  // agg: threads 0..tid composed
-  if (tid == NT - 1) s_tagg = agg;
-  __syncthreads();
 
   // lookback by wave 0: z at the start of this tile
   if (wv == 0) {
@@ -314,55 +342,63 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
   }
   __syncthreads();
 
-  // z at the end of each thread's run, then at its start (previous thread)
-  T zin[D], zend[D], z[D];
+  // pass 2: outputs chunk by chunk (a one-chunk tile is still in LDS)
+  T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
+  for (int c = 0; c < nch; c++) {
+    if (nch > 1) chunk_scan(c, true, agg, cn);
+    // z at the end of each thread's run, then at its start (previous thread)
+    T zin[D], zend[D], z[D];
 #pragma unroll
-  for (int i = 0; i < D; i++) zin[i] = s_zin[i];
+    for (int i = 0; i < D; i++) zin[i] = s_zin[i];
 #pragma unroll
-  for (int i = 0; i < D; i++) {
-    T acc = agg.b[i];
+    for (int i = 0; i < D; i++) {
+      T acc = agg.b[i];
 #pragma unroll
-    for (int k = 0; k < D; k++) acc += agg.A[i * D + k] * zin[k];
-    zend[i] = acc;
-  }
-  if (lane == PINT_WAVE - 1)
+      for (int k = 0; k < D; k++) acc += agg.A[i * D + k] * zin[k];
+      zend[i] = acc;
+    }
+    if (lane == PINT_WAVE - 1)
 #pragma unroll
-    for (int i = 0; i < D; i++) s_wz[wv][i] = zend[i];
-  __syncthreads();
+      for (int i = 0; i < D; i++) s_wz[wv][i] = zend[i];
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < D; i++) {
-    const T up = __shfl_up(zend[i], 1, PINT_WAVE);
-    z[i] = lane > 0 ? up : (wv > 0 ? s_wz[wv - 1][i] : zin[i]);
-  }
-  T out[S][D];
+    for (int i = 0; i < D; i++) {
+      const T up = __shfl_up(zend[i], 1, PINT_WAVE);
+      z[i] = lane > 0 ? up : (wv > 0 ? s_wz[wv - 1][i] : zin[i]);
+    }
+    T out[S][D];
 #pragma unroll
-  for (int s = 0; s < S; s++) {
-    if (tid * S + s < n_el) {
-      T t[D];
+    for (int s = 0; s < S; s++) {
+      if (tid * S + s < cn) {
+        T t[D];
 #pragma unroll
-      for (int i = 0; i < D; i++) {
-        T acc = myb[s * D + i];
+        for (int i = 0; i < D; i++) {
+          T acc = myb[s * D + i];
 #pragma unroll
-        for (int k = 0; k < D; k++) acc += myA[s * D * D + i * D + k] * z[k];
-        t[i] = acc;
-      }
+          for (int k = 0; k < D; k++) acc += myA[s * D * D + i * D + k] * z[k];
+          t[i] = acc;
+        }
 #pragma unroll
-      for (int i = 0; i < D; i++) {
-        z[i] = t[i];
-        out[s][i] = t[i];
+        for (int i = 0; i < D; i++) {
+          z[i] = t[i];
+          out[s][i] = t[i];
+        }
       }
     }
-  }
-  __syncthreads();  // the b staging area is rewritten with the outputs
+    __syncthreads();  // every thread has read s_zin, s_wz and its b run
+    if (tid == NT - 1)  // the next chunk starts where this one ends
 #pragma unroll
-  for (int s = 0; s < S; s++) {
-    if (tid * S + s < n_el)
+      for (int i = 0; i < D; i++) s_zin[i] = zend[i];
 #pragma unroll
-      for (int i = 0; i < D; i++) sb[tid * PB + s * D + i] = out[s][i];
+    for (int s = 0; s < S; s++) {
+      if (tid * S + s < cn)
+#pragma unroll
+        for (int i = 0; i < D; i++) sb[tid * PB + s * D + i] = out[s][i];
+    }
+    __syncthreads();
+    stage_out<T, RB, SH::VB, NT>(zg + (int64_t)c * CH * D, sb, cn * D, tid);
+    __syncthreads();  // the staging area is reloaded by the next chunk
   }
-  __syncthreads();
-  T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
-  stage_out<T, RB, SH::VB, NT>(zg, sb, n_el * D, tid);
 }
 
 // ------------------------------------------------------- d = 4 .. 8 ------

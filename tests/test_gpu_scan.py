@@ -12,9 +12,9 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
-# elements per tile of the small-d kernels (FP64): 256 threads x S elements for
-# d <= 3, 64 lanes x 64 elements for d >= 4
-SMALL_TILE = {1: 3072, 2: 1024, 3: 512, 4: 4096, 5: 4096, 6: 4096, 7: 4096, 8: 4096}
+# elements per tile of the small-d kernels (FP64): 8 chunks of 256 threads x S
+# elements for d <= 3, 64 lanes x 64 elements for d >= 4
+SMALL_TILE = {1: 24576, 2: 8192, 3: 4096, 4: 4096, 5: 4096, 6: 4096, 7: 4096, 8: 4096}
 
 
 def _ref(orc, A, b, z0):
@@ -75,7 +75,7 @@ def test_many_tiles_mixed(pint, orc, d, dtype):
     """Several times more tiles than workgroups resident on the device, three
     sequences of odd length so that later sequences start misaligned for
     vector loads and end ragged."""
-    N = 700 * SMALL_TILE[d] + 17
+    N = 100 * SMALL_TILE[d] + 17
     print(f"[scan] many tiles d={d} {dtype} N={N} B=3", flush=True)
     _check(pint, orc, d, N, 3, dtype, True, seed=40 + d)
 
