@@ -507,8 +507,8 @@ struct CoopCtl {
   int32_t done, st;
   int64_t k;
   unsigned long long rmax;  // final residual (bits of a non-negative double)
-  uint32_t err, pad0;
-  int64_t pad1;
+  uint32_t err, go;         // go: the last round whose update workgroup 0 released
+  uint32_t arrive, pad0;    // arrive: element passes completed, all workgroups
 };
 static_assert(sizeof(CoopCtl) == 64, "control block size");
 
@@ -538,6 +538,31 @@ __device__ __forceinline__ void coop_barrier(CoopCtl* c, int G, uint32_t& gen) {
     gen = target;
   }
   __syncthreads();
+}
+
+// One-way signals of a round (thread 0 of a workgroup; bounded waits raise
+// the error word and give up).  Every workgroup releases its elements by
+// incrementing `arrive`; only workgroup 0 waits for all of them.  Workgroup
+// 0 releases the committed update by storing the round in `go`; only the
+// others wait for it.
+__device__ __forceinline__ void coop_arrive(CoopCtl* c) {
+  __threadfence();
+  atomicAdd(&c->arrive, 1u);
+}
+__device__ __forceinline__ void coop_wait_at_least(CoopCtl* c, const uint32_t* word, uint32_t target) {
+  for (uint64_t it = 0;
+       __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; it++) {
+    if (it > (1ull << 28)) {
+      atomicOr(&c->err, 1u);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __threadfence();
+}
+__device__ __forceinline__ void coop_release_go(CoopCtl* c, uint32_t round) {
+  __threadfence();
+  __hip_atomic_store(&c->go, round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // G workgroups per instance (windowed mode): all of them build the
@@ -623,7 +648,7 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
     }
   }
   coop_barrier(c, G, gen);
-  for (;;) {
+  for (uint32_t rnd = 1;; rnd++) {
     if (tid == 0) {
       s_win[0] = c->lo;
       s_win[1] = c->hi;
@@ -634,8 +659,11 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
     const int64_t base = s_win[0];
     const int64_t slen = SPEC ? ((Tn - base + 1) < Wcap ? (Tn - base + 1) : Wcap) : s_win[1] - base + 1;
     dn_elements<T, S>(sm, dt, X, base, slen, g, G, AT, bb, SPEC ? hn : nullptr);
-    coop_barrier(c, G, gen);
+    __syncthreads();  // this workgroup's element stores are issued
+    if (tid == 0) coop_arrive(c);
     if (g == 0) {
+      if (tid == 0) coop_wait_at_least(c, &c->arrive, (uint32_t)G * rnd);
+      __syncthreads();
       int64_t p = base, next = 0;
       int done = 0;
       bool fold = true;
@@ -703,8 +731,12 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
           decide(p);
         }
       }
+      __syncthreads();  // the committed update and the next window are written
+      if (tid == 0) coop_release_go(c, rnd);
+    } else {
+      if (tid == 0) coop_wait_at_least(c, &c->go, rnd);
+      __syncthreads();
     }
-    coop_barrier(c, G, gen);
   }
   // final residual: steps split over the G workgroups
   const double r = dn_resid_max<T, S>(sm, dt, X, Tn, 1 + g, G);
