@@ -54,8 +54,8 @@ def measured_traffic(kernel: str, T: int, window: int):
             rec = json.load(f)["kernels"][kernel]
     except (OSError, KeyError, ValueError):
         return None, "no counter record"
-    if T != 65536 or window != 32:
-        return None, "counters were taken at T=65536, window 32"
+    if T != rec.get("T", 65536) or window != rec.get("window", 32):
+        return None, "counters were taken at T=%d, window %d" % (rec.get("T", 65536), rec.get("window", 32))
     src = "".join(open(os.path.join(ROOT, p)).read() for p in rec["sources"])
     if hashlib.sha256(src.encode()).hexdigest() != rec["source_sha256"]:
         return None, "kernel changed since the counters were taken"
@@ -236,7 +236,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--T", type=int, default=65536)
-    ap.add_argument("--window", type=int, default=32)
+    ap.add_argument("--window", type=int, default=0,
+                    help="Newton window; 0 = picked by the autotuner among 32, 48, 64")
     ap.add_argument("--cpu-sample", type=int, default=65536, help="oracle prefix length (steps)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
@@ -257,6 +258,16 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    tuned = None
+    if args.window <= 0:  # the autotuner's window for this workload (outside the timed region)
+        from paper_2511_01465_amd import autotune
+        wl = W.lorenz96(T=args.T)
+        tuned = autotune.tune_window(P.LORENZ96, torch.tensor(wl.x0, device=dev),
+                                     torch.tensor(wl.params, device=dev), wl.dt, args.T, tol=wl.tol,
+                                     cache=None)
+        args.window = tuned["window"]
+        print(f"[bench] tuned window {args.window}: " +
+              ", ".join(f"W={t['window']} {t['ms']:.1f} ms" for t in tuned["trials"]), file=sys.stderr, flush=True)
     w = W.lorenz96(T=args.T, window=args.window)
     T, d, B = args.T, w.d, w.B
     x0 = torch.tensor(w.x0, device=dev)
@@ -411,6 +422,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"lorenz96 d={d} F=8 dt=0.005 T={T} B={B} seed=2, windowed "
                                f"Newton W={args.window}, tol 1e-10",
+                   "window": args.window,
+                   "window_tuning": None if tuned is None else
+                   {str(t["window"]): round(t["ms"], 2) for t in tuned["trials"]},
                    "parallelism": "single GPU"},
         "solve": {"status": st, "updates": n_iter, "final_resid": r_final, "fp64_defect": defect},
         "roofline": roofline,

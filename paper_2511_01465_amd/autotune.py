@@ -162,3 +162,41 @@ def tune_scan(d: int, B: int, N: int, dtype: int = F64, *, tiles: Sequence[int] 
     store[key] = out
     _store_cache(cache, store)
     return out
+
+
+def tune_window(system, x0: torch.Tensor, params: torch.Tensor, dt: float, T: int, *,
+                tol: float = 1e-10, guard: float = 1e6, windows: Sequence[int] = (32, 48, 64),
+                reps: int = 1, cache: Optional[str] = DEFAULT_CACHE, force: bool = False,
+                stream=None) -> dict:
+    """Pick the Newton window W of a uniform-horizon solve (pint_solve): the
+    fastest candidate whose every instance converged.  A longer window
+    costs more per update and needs fewer updates, up to the point where the
+    linearisation across it fails and the guard keeps cutting updates."""
+    from . import solve
+    key = "window|sys=%d|d=%d|dtype=%d|B=%d|T=%d|dt=%g|tol=%g|guard=%g|%s" % (
+        _sys_id(system), x0.shape[-1], _dtype_code(x0), x0.shape[0] if x0.dim() > 1 else 1, T, dt,
+        tol, guard, _device_name(x0.device))
+    store = _load_cache(cache)
+    if not force and key in store:
+        return store[key]
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    trials = []
+    for wv in windows:
+        res = {}
+
+        def fn():
+            res["o"] = solve(system, x0, params, dt, T, tol=tol, guard=guard, window=int(wv),
+                             stream=stream)
+
+        ms = _time_ms(fn, reps, stream)
+        st = res["o"][3]
+        trials.append({"window": int(wv), "ms": ms, "ok": bool((st == 0).all()),
+                       "updates_max": int(res["o"][1].max())})
+    ok = [t for t in trials if t["ok"]]
+    if not ok:
+        raise PintError("autotune: no window converged on every instance")
+    best = min(ok, key=lambda t: t["ms"])
+    out = {"window": best["window"], "ms": best["ms"], "trials": trials, "key": key}
+    store[key] = out
+    _store_cache(cache, store)
+    return out
