@@ -48,6 +48,31 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Butterfly exchanges inside each group of four lanes, as DPP quad
+// permutations of a VALU move (no LDS round trip): dpp_xor1 returns the value
+// of lane l^1, dpp_xor2 that of lane l^2.  Every lane of the quad must be
+// active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_quad(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v) {
+  const int lo = dpp_quad<CTRL>(__double2loint(v)), hi = dpp_quad<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_quad(float v) {
+  return __int_as_float(dpp_quad<CTRL>(__float_as_int(v)));
+}
+template <typename T>
+__device__ __forceinline__ T dpp_xor1(T v) { return dpp_quad<DPP_QUAD_XOR1>(v); }
+template <typename T>
+__device__ __forceinline__ T dpp_xor2(T v) { return dpp_quad<DPP_QUAD_XOR2>(v); }
+
 // Block-wide reductions for blockDim.x = NT (a multiple of 64).  `red` is a
 // shared scratch of at least NT/64 doubles; the result is returned to every
 // thread.  Contains two __syncthreads.

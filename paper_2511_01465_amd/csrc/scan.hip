@@ -675,8 +675,8 @@ struct Mfma<float> {  // v_mfma_f32_16x16x4f32: acc (lane l, reg r) = (4(l/16) +
   __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
 };
 
-// STAT ("stationary product", FP64 with D a multiple of 64): the running
-// product stays in the MFMA accumulators, each wave owning NTL/4 column tiles
+// STAT ("stationary product", FP64): the running product stays in the MFMA
+// accumulators, each wave owning ceil(NTL/4) column tiles (zero padded to DP)
 // -- the FP64 16x16x4 accumulator layout (lane l, reg r) = (l/16 + 4r, l%16)
 // is exactly the B-operand layout of the next product's k-steps -- and only
 // the element being folded passes through LDS (rows padded to DP + 4).
@@ -686,8 +686,8 @@ struct DenseScanShape {
   static constexpr int DP = (D + 15) / 16 * 16;    // padded to MFMA tiles
   static constexpr int NTL = DP / 16;               // 16x16 tiles per dimension
   static constexpr int NT = 256, NW = 4;
-  static constexpr bool STAT = sizeof(T) == 8 && D % 64 == 0;
-  static constexpr int CT = NTL / NW;               // STAT: column tiles per wave
+  static constexpr bool STAT = sizeof(T) == 8 && D % 2 == 0;
+  static constexpr int CT = (NTL + NW - 1) / NW;    // STAT: column tiles per wave
   static constexpr int PS = STAT ? DP + 4 : ((DP % 32 == 0) ? DP + 16 : DP);  // LDS row stride
   static constexpr int RT = (NTL + NW - 1) / NW;   // row tiles per wave
 };
@@ -731,6 +731,7 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
   T* sz = sq + DP;                                  // z vector
   T* st = sz + DP;                                  // scratch vector
   T* sq2 = st + DP;                                 // STAT: second b-part buffer
+  T* sbm = sq2 + DP;                                // STAT: b_m of the element being folded
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
   if (tid == 0) s_tile = atomicAdd(a.counter, 1u);
@@ -745,83 +746,160 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
 
   if constexpr (SH::STAT) {
     // ---- stationary product: P in accumulators, A_m staged through LDS ----
-    static_assert(D == DP && (DP * DP) % (2 * NT) == 0, "stationary shape");
-    constexpr int CT = SH::CT, NPF = DP * DP / (2 * NT);  // double2 loads per thread per element
+    // AUG (D < DP): the element is staged as the augmented matrix
+    // [[A_m, b_m], [0, 1]] in the padded rows and columns, and the product
+    // holds [[P, q], [0, 1]], so the MFMA products carry the b-part too.
+    static_assert(D % 2 == 0, "stationary shape: element pairs");
+    constexpr bool AUG = D < DP;
+    constexpr int CT = SH::CT, NPAIR = D * D / 2, NPF = (NPAIR + NT - 1) / NT;  // double2 loads per thread
     typedef double v2_t __attribute__((ext_vector_type(2)));
-    const int col0 = wv * CT;
+    // this wave's column tiles col0 .. col0+CT-1 (those < NTL); wave-uniform,
+    // so the tests below are scalar branches around whole MFMA sequences
+    // (a wave with only some of its CT tiles in range exists only when CT
+    // does not divide NTL; otherwise a wave has all of them or none)
+    constexpr bool PARTIAL = NTL % CT != 0;
+    const int col0 = __builtin_amdgcn_readfirstlane(wv * CT);
+    const bool mf_any = col0 < NTL, mf_full = col0 + CT <= NTL;
+    auto col_ok = [&](int ct) { return !PARTIAL || mf_full || col0 + ct < NTL; };
+    // the staging area starts zero except the augmented corner
+    for (int i = tid; i < DP * PS; i += NT) sP[i] = (AUG && i == D * PS + D) ? T(1) : T(0);
     pint_d4 P[NTL][CT];
 #pragma unroll
     for (int it = 0; it < NTL; it++)
 #pragma unroll
       for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-        for (int r = 0; r < 4; r++)
-          P[it][ct][r] = Aseq[(16 * it + lane / 16 + 4 * r) * D + 16 * (col0 + ct) + lane % 16];
-    for (int i = tid; i < DP; i += NT) sq[i] = bseq[i];
-    v2_t pf[NPF];
-    auto prefetch = [&](int m) {
+        for (int r = 0; r < 4; r++) {
+          const int row = 16 * it + lane / 16 + 4 * r, col = 16 * (col0 + ct) + lane % 16;
+          T v = (row < D && col < D) ? Aseq[row * D + col] : T(0);
+          if (AUG && col == D) v = row < D ? bseq[row] : (row == D ? T(1) : T(0));
+          P[it][ct][r] = v;
+        }
+    if (!AUG)
+      for (int i = tid; i < DP; i += NT) sq[i] = i < D ? bseq[i] : T(0);
+    // the next PF elements in a register ring (slot u holds element m0 + u),
+    // b_m included: a load issued after the ring's would make its use wait
+    // for the whole ring.  The barriers in the loop order LDS only, so the
+    // ring's loads stay in flight across them.
+    constexpr int PF = NPF >= 16 ? 1 : (NPF >= 8 ? 2 : 4);
+    constexpr int QC = (D * 4 <= NT) ? 4 : 2;  // !AUG b-part: threads per row
+    v2_t pf[PF][NPF];
+    T pb[PF];
+    const int bi = tid < D ? tid : 0;
+    // (unconditional loads, the last pair re-read past the end: a load
+    // under a divergent branch makes the compiler's wait counts conservative
+    // and the ring drains at every element)
+    auto prefetch = [&](int m, v2_t (&slot)[NPF], T& bv) {
       const v2_t* src = reinterpret_cast<const v2_t*>(Aseq + (int64_t)m * D * D);
 #pragma unroll
-      for (int j = 0; j < NPF; j++) pf[j] = src[j * NT + tid];
+      for (int j = 0; j < NPF; j++) slot[j] = src[min(j * NT + tid, NPAIR - 1)];
+      bv = bseq[(int64_t)m * D + bi];
     };
-    if (n_el > 1) prefetch(1);
-    for (int m = 1; m < n_el; m++) {
-      const T* qo = (m & 1) ? sq : sq2;  // b-part after element m-1
-      T* qn = (m & 1) ? sq2 : sq;        // after element m
-      __syncthreads();  // A_{m-1} and the old b-part no longer read
+#pragma unroll
+    for (int u = 0; u < PF; u++) prefetch(min(1 + u, n_el - 1), pf[u], pb[u]);
+    // every load complete at the loop entry: one still pending there (in
+    // whatever order the compiler issued the ring's first fill) would set
+    // the wait counts inside the loop to zero, draining the ring each time
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();  // the staging area and b-part are visible
+    // one element: stage slot, refill it with element m + PF, fold
+    auto fold_one = [&](const int m, v2_t (&slot)[NPF], T& bslot) __attribute__((always_inline)) {
+      lds_barrier();  // A_{m-1} (and the old b-part) no longer read
 #pragma unroll
       for (int j = 0; j < NPF; j++) {
-        const int q = 2 * (j * NT + tid), i = q / D, k = q % D;
-        sP[i * PS + k] = pf[j][0];
-        sP[i * PS + k + 1] = pf[j][1];
-      }
-      __syncthreads();  // A_m staged
-      if (m + 1 < n_el) prefetch(m + 1);  // lands while the products run
-      {  // b-part: A_m q + b_m
-        constexpr int QC = 2;
-        const int i = tid / QC, h = tid % QC;
-        T part = T(0);
-        if (i < D)
-#pragma unroll 8
-          for (int k = 0; k < D / QC; k++) part += sP[i * PS + h * (D / QC) + k] * qo[h * (D / QC) + k];
-        part += __shfl_xor(part, 1, PINT_WAVE);
-        if (i < D && h == 0) qn[i] = part + bseq[(int64_t)m * D + i];
-      }
-      pint_d4 Pn[NTL][CT];
-#pragma unroll
-      for (int it = 0; it < NTL; it++)
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) Pn[it][ct] = pint_d4{};
-#pragma unroll
-      for (int kt = 0; kt < NTL; kt++) {
-#pragma unroll
-        for (int qk = 0; qk < 4; qk++) {
-#pragma unroll
-          for (int it = 0; it < NTL; it++) {
-            const double av = sP[(16 * it + lane % 16) * PS + 16 * kt + 4 * qk + lane / 16];
-#pragma unroll
-            for (int ct = 0; ct < CT; ct++)
-              Pn[it][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, P[kt][ct][qk], Pn[it][ct], 0, 0, 0);
-          }
+        if (j * NT + tid < NPAIR) {
+          const int q = 2 * (j * NT + tid), i = q / D, k = q % D;
+          sP[i * PS + k] = slot[j][0];
+          sP[i * PS + k + 1] = slot[j][1];
         }
       }
+      // b_m staged too (read back from LDS, not kept in a register across the
+      // slot's refill: that makes the compiler wait for the refill)
+      if (tid < D) {
+        if (AUG) sP[tid * PS + D] = bslot;
+        else sbm[tid] = bslot;
+      }
+      lds_barrier();  // A_m staged
+      // refilled unconditionally (the last element again near the end): a
+      // skipped refill on some path would shrink the wait counts everywhere
+      prefetch(min(m + PF, n_el - 1), slot, bslot);  // lands while later elements run
+      if (mf_any) {
+        pint_d4 Pn[NTL][CT];
+#pragma unroll
+        for (int it = 0; it < NTL; it++)
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++) Pn[it][ct] = pint_d4{};
+#pragma unroll
+        for (int kt = 0; kt < NTL; kt++) {
+#pragma unroll
+          for (int qk = 0; qk < 4; qk++) {
+#pragma unroll
+            for (int it = 0; it < NTL; it++) {
+              const double av = sP[(16 * it + lane % 16) * PS + 16 * kt + 4 * qk + lane / 16];
+#pragma unroll
+              for (int ct = 0; ct < CT; ct++)
+                if (col_ok(ct))
+                  Pn[it][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, P[kt][ct][qk], Pn[it][ct], 0, 0, 0);
+            }
+          }
+        }
+#pragma unroll
+        for (int it = 0; it < NTL; it++)
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++) P[it][ct] = Pn[it][ct];
+      }
+      if constexpr (!AUG) {  // b-part A_m q + b_m, four chains per thread
+        const T* qo = (m & 1) ? sq : sq2;  // after element m-1
+        T* qn = (m & 1) ? sq2 : sq;        // after element m
+        constexpr int SEG = D / QC;
+        static_assert(SEG % 4 == 0, "b-part chains");
+        const int i = tid / QC, h = tid % QC;
+        if (i < D) {
+          const T* row = sP + i * PS + h * SEG;
+          const T* qv = qo + h * SEG;
+          T c0 = h == 0 ? sbm[i] : T(0), c1 = T(0), c2 = T(0), c3 = T(0);
+#pragma unroll
+          for (int k = 0; k < SEG; k += 4) {
+            c0 += row[k] * qv[k];
+            c1 += row[k + 1] * qv[k + 1];
+            c2 += row[k + 2] * qv[k + 2];
+            c3 += row[k + 3] * qv[k + 3];
+          }
+          T part = (c0 + c1) + (c2 + c3);
+          part += dpp_xor1(part);
+          if (QC == 4) part += dpp_xor2(part);
+          if (h == 0) qn[i] = part;
+        }
+      }
+    };
+    // whole groups of PF elements, then the rest: no exit from inside a
+    // group, so on every path through the loop each slot is refilled once
+    // per group and the wait counts keep the other slots' loads in flight
+    int m0 = 1;
+    for (; m0 + PF <= n_el; m0 += PF)
+#pragma unroll
+      for (int u = 0; u < PF; u++) fold_one(m0 + u, pf[u], pb[u]);
+#pragma unroll
+    for (int u = 0; u + 1 < PF; u++)
+      if (m0 + u < n_el) fold_one(m0 + u, pf[u], pb[u]);
+    // the tile's product into LDS (row stride PS) for the rest of the kernel
+    __syncthreads();
+    if (mf_any)
 #pragma unroll
       for (int it = 0; it < NTL; it++)
 #pragma unroll
-        for (int ct = 0; ct < CT; ct++) P[it][ct] = Pn[it][ct];
-    }
-    // the tile's product into LDS (row stride PS) for the rest of the kernel
-    __syncthreads();
+        for (int ct = 0; ct < CT; ct++)
+          if (col_ok(ct))
 #pragma unroll
-    for (int it = 0; it < NTL; it++)
-#pragma unroll
-      for (int ct = 0; ct < CT; ct++)
-#pragma unroll
-        for (int r = 0; r < 4; r++)
-          sP[(16 * it + lane / 16 + 4 * r) * PS + 16 * (col0 + ct) + lane % 16] = P[it][ct][r];
-    if ((n_el & 1) == 0)  // the final b-part is in sq2
+            for (int r = 0; r < 4; r++)
+              sP[(16 * it + lane / 16 + 4 * r) * PS + 16 * (col0 + ct) + lane % 16] = P[it][ct][r];
+    if (!AUG && (n_el & 1) == 0)  // the final b-part is in sq2
       for (int i = tid; i < DP; i += NT) sq[i] = sq2[i];
     __syncthreads();
+    if (AUG) {  // the b-part is column D of the product
+      for (int i = tid; i < DP; i += NT) sq[i] = i < D ? sP[i * PS + D] : T(0);
+      __syncthreads();
+    }
   } else {
     // P <- A_0 (zero padded), q <- b_0
     for (int idx = tid; idx < DP * DP; idx += NT) {
@@ -943,33 +1021,50 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
     const int i = tid / QC, h = tid % QC;
     const bool act = i < D;
     const int ii = act ? i : 0;
-    T cur[SEG], nxt[SEG], bc = T(0), bn = T(0);
+    // ring of the next PO elements' row segments (slot u: element m0 + u)
+    constexpr int PO = SEG > 16 ? 2 : 4;
+    T ring[PO][SEG], rb[PO];
+    auto fetch = [&](int m, T (&seg)[SEG], T& bv) {
+      const T* Am = Aseq + (int64_t)m * D * D + (int64_t)ii * D + h * SEG;
 #pragma unroll
-    for (int k = 0; k < SEG; k++) cur[k] = Aseq[(int64_t)ii * D + h * SEG + k];
-    bc = bseq[ii];
-    for (int m = 0; m < n_el; m++) {
-      if (m + 1 < n_el) {
-        const T* An = Aseq + (int64_t)(m + 1) * D * D + (int64_t)ii * D + h * SEG;
+      for (int k = 0; k < SEG; k++) seg[k] = Am[k];
+      bv = bseq[(int64_t)m * D + ii];
+    };
 #pragma unroll
-        for (int k = 0; k < SEG; k++) nxt[k] = An[k];
-        bn = bseq[(int64_t)(m + 1) * D + ii];
+    for (int u = 0; u < PO; u++) fetch(min(u, n_el - 1), ring[u], rb[u]);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): as in the fold
+    // z alternates between sz (even m reads it) and st (odd m reads it): a
+    // buffer is rewritten only after the barrier that ends its readers
+    auto out_one = [&](const int m, T (&seg)[SEG], T& bv) __attribute__((always_inline)) {
+      const T* zc = (m & 1) ? st : sz;
+      T* zn = (m & 1) ? sz : st;
+      // b_m enters at the head of the chain (lane h == 0), so the slot's old
+      // value is dead before its refill is issued
+      T c0 = h == 0 ? bv : T(0), c1 = T(0);
+#pragma unroll
+      for (int k = 0; k + 1 < SEG; k += 2) {
+        c0 += seg[k] * zc[h * SEG + k];
+        c1 += seg[k + 1] * zc[h * SEG + k + 1];
       }
-      T part = T(0);
-#pragma unroll
-      for (int k = 0; k < SEG; k++) part += cur[k] * sz[h * SEG + k];
-#pragma unroll
-      for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
-      if (act && h == 0) st[i] = part + bc;
-      lds_barrier();
-      if (tid < D) {
-        sz[tid] = st[tid];
-        zg[(int64_t)m * D + tid] = st[tid];
+      if (SEG & 1) c0 += seg[SEG - 1] * zc[h * SEG + SEG - 1];
+      T part = c0 + c1;
+      if (QC >= 2) part += dpp_xor1(part);
+      if (QC >= 4) part += dpp_xor2(part);
+      const T zv = part;
+      fetch(min(m + PO, n_el - 1), seg, bv);  // unconditional: see the fold
+      if (act && h == 0) {
+        zn[i] = zv;
+        zg[(int64_t)m * D + i] = zv;
       }
       lds_barrier();
+    };
+    int m0 = 0;  // whole groups, then the rest (as in the fold)
+    for (; m0 + PO <= n_el; m0 += PO)
 #pragma unroll
-      for (int k = 0; k < SEG; k++) cur[k] = nxt[k];
-      bc = bn;
-    }
+      for (int u = 0; u < PO; u++) out_one(m0 + u, ring[u], rb[u]);
+#pragma unroll
+    for (int u = 0; u + 1 < PO; u++)
+      if (m0 + u < n_el) out_one(m0 + u, ring[u], rb[u]);
   }
 }
 
