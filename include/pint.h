@@ -221,6 +221,24 @@ pint_status pint_affine_scan(int32_t d, int64_t B, int64_t N, int32_t dtype,
                              void* z, int32_t tile, void* ws, size_t ws_bytes,
                              pint_stream_t stream);
 
+/* pint_affine_scan_band — pint_affine_scan for elements whose A is
+ * cyclically banded: A_n(i, (i + k - boff) mod d) = band_n[i][k] for
+ * k < bw, every other entry exactly zero (the RK4 Jacobian of a
+ * short-stencil system such as Lorenz-96, eq. lorenz96-model, or its
+ * transpose in the adjoint).  Same recursion, output and workspace rules as
+ * pint_affine_scan; band [B][N][d][bw] row-major (16-byte aligned for
+ * FP64, 8-byte for FP32), b [B][N][d].  The running products of a tile are
+ * dense; only the elements are read as bands (d*bw values instead of d*d).
+ * Supported shapes: d = 40, bw = 13, boff = 8 (the Lorenz-96 step
+ * Jacobian) or 4 (its transpose).  Returns PINT_ERR_UNSUPPORTED for other
+ * shapes, PINT_ERR_INVALID_ARG for a misaligned band. */
+size_t pint_scan_band_workspace_bytes(int32_t d, int32_t bw, int32_t boff, int64_t B,
+                                      int64_t N, int32_t tile, int32_t dtype);
+pint_status pint_affine_scan_band(int32_t d, int32_t bw, int32_t boff, int64_t B, int64_t N,
+                                  int32_t dtype, const void* band, const void* b,
+                                  const void* z0, void* z, int32_t tile, void* ws,
+                                  size_t ws_bytes, pint_stream_t stream);
+
 /*
  * pint_adjoint — gradient of a trajectory loss L(x_1..x_T) through the
  * discrete solution map x_n = Phi(x_{n-1}; theta) of a uniform batch:

@@ -53,6 +53,7 @@ _lib = None
 EXPORTS = ["pint_n_params", "pint_status_string", "pint_supported", "pint_workspace_bytes",
            "pint_solve_varlen", "pint_solve", "pint_seq_integrate", "pint_residual",
            "pint_elements", "pint_scan_workspace_bytes", "pint_affine_scan",
+           "pint_scan_band_workspace_bytes", "pint_affine_scan_band",
            "pint_adjoint_workspace_bytes", "pint_adjoint", "pint_graph_capture_varlen",
            "pint_graph_launch", "pint_graph_destroy"]
 
@@ -79,6 +80,9 @@ def load(path: str = LIB_PATH):
         "pint_elements": (C.c_int, [SP, i64, vp, dbl, i64, i32, vp, vp, vp, vp]),
         "pint_scan_workspace_bytes": (sz, [i32, i64, i64, i32, i32]),
         "pint_affine_scan": (C.c_int, [i32, i64, i64, i32, vp, vp, vp, vp, i32, vp, sz, vp]),
+        "pint_scan_band_workspace_bytes": (sz, [i32, i32, i32, i64, i64, i32, i32]),
+        "pint_affine_scan_band": (C.c_int, [i32, i32, i32, i64, i64, i32, vp, vp, vp, vp, i32, vp,
+                                            sz, vp]),
         "pint_adjoint_workspace_bytes": (sz, [SP, i64, i64, i64, i32]),
         "pint_adjoint": (C.c_int, [SP, i64, vp, dbl, i64, i32, vp, vp, vp, vp, i64, vp, sz, vp]),
         "pint_graph_capture_varlen": (C.c_int, [SP, i64, vp, dbl, vp, i64, OP, vp, vp, vp, vp, vp, sz,
@@ -205,6 +209,16 @@ def pint_scan_workspace_bytes(d, B, N, tile, dtype) -> int:
 def pint_affine_scan(d, B, N, dtype, A, b, z0, z, tile, ws, stream=None) -> int:
     return load().pint_affine_scan(d, B, N, dtype, _ptr(A), _ptr(b), _ptr(z0), _ptr(z), tile,
                                    _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream))
+
+
+def pint_scan_band_workspace_bytes(d, bw, boff, B, N, tile, dtype) -> int:
+    return load().pint_scan_band_workspace_bytes(d, bw, boff, B, N, tile, dtype)
+
+
+def pint_affine_scan_band(d, bw, boff, B, N, dtype, band, b, z0, z, tile, ws, stream=None) -> int:
+    return load().pint_affine_scan_band(d, bw, boff, B, N, dtype, _ptr(band), _ptr(b), _ptr(z0),
+                                        _ptr(z), tile, _ptr(ws), 0 if ws is None else ws.numel(),
+                                        _stream(stream))
 
 
 def pint_adjoint_workspace_bytes(sysd, B, T, seg, dtype) -> int:
@@ -432,6 +446,20 @@ def affine_scan(A: torch.Tensor, b: torch.Tensor, z0: Optional[torch.Tensor] = N
     _check(pint_affine_scan(d, B, N, dtc, A.contiguous(), b.contiguous(),
                             None if z0 is None else z0.contiguous(), z, tile, ws, stream),
            "pint_affine_scan")
+    return z
+
+
+def affine_scan_band(band: torch.Tensor, b: torch.Tensor, boff: int, z0: Optional[torch.Tensor] = None,
+                     tile: int = 0, stream=None):
+    """As affine_scan for cyclically banded A: band [B, N, d, bw] with
+    A_n(i, (i + k - boff) mod d) = band[b, n, i, k]."""
+    B, N, d, bw = band.shape
+    dtc = _dtype_code(band)
+    z = torch.empty((B, N, d), dtype=band.dtype, device=band.device)
+    ws = _workspace(pint_scan_band_workspace_bytes(d, bw, boff, B, N, tile, dtc), band.device)
+    _check(pint_affine_scan_band(d, bw, boff, B, N, dtc, band.contiguous(), b.contiguous(),
+                                 None if z0 is None else z0.contiguous(), z, tile, ws, stream),
+           "pint_affine_scan_band")
     return z
 
 

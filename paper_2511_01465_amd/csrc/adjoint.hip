@@ -25,7 +25,8 @@ struct AdjArgs {
   const void* g;
   double dt;
   int64_t i_lo, i_hi;  // element range [i_lo, i_hi) of this segment
-  void* A;             // [B][i_hi-i_lo][D][D]  (row-major J^T)
+  void* A;             // [B][i_hi-i_lo][D][D]  (row-major J^T), or its band
+                       // [B][i_hi-i_lo][D][BW] for a banded system
   void* b;             // [B][i_hi-i_lo][D]
 };
 
@@ -112,15 +113,26 @@ __global__ __launch_bounds__(S::NT) void k_adj_elems_dense(AdjArgs a) {
     const int64_t gi = g0 + sl;
     if (gi >= total) continue;
     const int64_t i = a.i_lo + gi % L;
-    T* Ao = static_cast<T*>(a.A) + gi * D * D;
-    if (i == 0) {
-      // identity (multiplies z_0 = 0)
-      if (sub == 0)
-        for (int r = 0; r < D * D; r++) Ao[r] = (r / D == r % D) ? T(1) : T(0);
-      continue;
+    if constexpr (S::BANDED) {
+      // the transposed band (row j of J^T from column j of J)
+      T* Ao = static_cast<T*>(a.A) + gi * D * S::BW;
+      if (i == 0) {  // identity: the diagonal is band column BOFFT
+        if (sub == 0)
+          for (int r = 0; r < D * S::BW; r++) Ao[r] = (r % S::BW == S::BOFFT) ? T(1) : T(0);
+        continue;
+      }
+      S::jac_bandT_thread(&s_stage[sl], s_P[sl], sub, (T)a.dt, Ao);
+    } else {
+      T* Ao = static_cast<T*>(a.A) + gi * D * D;
+      if (i == 0) {
+        // identity (multiplies z_0 = 0)
+        if (sub == 0)
+          for (int r = 0; r < D * D; r++) Ao[r] = (r / D == r % D) ? T(1) : T(0);
+        continue;
+      }
+      // J(i, j) -> Ao[j * D + i]: the row-major transpose
+      S::jac_thread(&s_stage[sl], s_P[sl], sub, (T)a.dt, Ao, 1, D);
     }
-    // J(i, j) -> Ao[j * D + i]: the row-major transpose
-    S::jac_thread(&s_stage[sl], s_P[sl], sub, (T)a.dt, Ao, 1, D);
   }
 }
 
@@ -244,19 +256,26 @@ struct AdjLayout {
   size_t off_A, off_b, off_lam, off_zs, off_carry, off_scan, scan_bytes, total;
 };
 
-static AdjLayout adj_layout(int d, int64_t B, int64_t T, int64_t seg, int dtype) {
+// Band width of the adjoint elements of a banded system (0: dense).
+static int adj_band(int system, int d) {
+  return (system == 5 && d == 40) ? DSysL96<double, 40>::BW : 0;
+}
+
+static AdjLayout adj_layout(int system, int d, int64_t B, int64_t T, int64_t seg, int dtype) {
   AdjLayout l{};
   const size_t s = dtype == 0 ? 8 : 4;
   const int64_t T1 = T + 1;
+  const int bw = adj_band(system, d);
   l.L = (seg > 0 && seg < T1) ? seg : T1;
   size_t o = 0;
-  l.off_A = o;     o += align_up((size_t)B * l.L * d * d * s);
+  l.off_A = o;     o += align_up((size_t)B * l.L * d * (bw ? bw : d) * s);
   l.off_b = o;     o += align_up((size_t)B * l.L * d * s);
   l.off_lam = o;   o += align_up((size_t)B * T1 * d * s);
   l.off_zs = o;    o += align_up((size_t)B * l.L * d * s);
   l.off_carry = o; o += align_up((size_t)B * d * s);
   l.off_scan = o;
-  l.scan_bytes = scan_ws_bytes(d, B, l.L, 0, dtype);
+  l.scan_bytes = bw ? scan_band_ws_bytes(d, bw, DSysL96<double, 40>::BOFFT, B, l.L, 0, dtype)
+                   : scan_ws_bytes(d, B, l.L, 0, dtype);
   o += align_up(l.scan_bytes);
   l.total = o;
   return l;
@@ -264,14 +283,14 @@ static AdjLayout adj_layout(int d, int64_t B, int64_t T, int64_t seg, int dtype)
 
 size_t adjoint_ws_bytes(int system, int d, int64_t B, int64_t T, int64_t seg, int dtype) {
   if (!small_supported(system, d) && !dense_supported(system, d)) return 0;
-  return adj_layout(d, B, T, seg, dtype).total;
+  return adj_layout(system, d, B, T, seg, dtype).total;
 }
 
 int adjoint(const SolveArgs& sa, const void* g, void* dL_dx0, void* dL_dth, int64_t seg) {
   const int d = sa.d;
   const int64_t B = sa.B, T = sa.T_uniform, T1 = T + 1;
   if (sa.system == 6 && dL_dth) return ST_UNSUPPORTED;  // Kuramoto: dL/dx0 only
-  const AdjLayout lay = adj_layout(d, B, T, seg, sa.dtype);
+  const AdjLayout lay = adj_layout(sa.system, d, B, T, seg, sa.dtype);
   if (!sa.ws || sa.ws_bytes < lay.total) return ST_WORKSPACE;
   char* w = static_cast<char*>(sa.ws);
   hipStream_t st = sa.stream;
@@ -323,9 +342,22 @@ int adjoint(const SolveArgs& sa, const void* g, void* dL_dx0, void* dL_dth, int6
       if (hipGetLastError() != hipSuccess) return ST_DEVICE;
       // the scan writes straight into lambda when there is one segment
       T_* zout = segmented ? zs : lam;
-      // affine_scan needs B sequences of L elements: contiguous in A/b
-      int rc = affine_scan(D, B, L, sa.dtype, a.A, a.b, lo == 0 ? nullptr : carry, zout, 0,
+      // the scan needs B sequences of L elements: contiguous in A/b
+      int rc = ST_OK;
+      auto dense_scan = [&]() {
+        return affine_scan(D, B, L, sa.dtype, a.A, a.b, lo == 0 ? nullptr : carry, zout, 0,
                            w + lay.off_scan, lay.scan_bytes, st);
+      };
+      if constexpr (decltype(is_small)::value) {
+        rc = dense_scan();
+      } else {
+        if constexpr (S::BANDED)
+          rc = affine_scan_band(D, S::BW, S::BOFFT, B, L, sa.dtype, a.A, a.b,
+                                lo == 0 ? nullptr : carry, zout, 0, w + lay.off_scan,
+                                lay.scan_bytes, st);
+        else
+          rc = dense_scan();
+      }
       if (rc) return rc;
       if (segmented) {
         const int64_t n = B * L * D;

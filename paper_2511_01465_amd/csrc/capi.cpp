@@ -285,6 +285,25 @@ pint_status pint_affine_scan(int32_t d, int64_t B, int64_t N, int32_t dtype, con
                                   reinterpret_cast<hipStream_t>(stream));
 }
 
+size_t pint_scan_band_workspace_bytes(int32_t d, int32_t bw, int32_t boff, int64_t B, int64_t N,
+                                      int32_t tile, int32_t dtype) {
+  if (dtype != PINT_F64 && dtype != PINT_F32) return 0;
+  return scan_band_ws_bytes(d, bw, boff, B, N, tile, dtype);
+}
+
+pint_status pint_affine_scan_band(int32_t d, int32_t bw, int32_t boff, int64_t B, int64_t N,
+                                  int32_t dtype, const void* band, const void* b, const void* z0,
+                                  void* z, int32_t tile, void* ws, size_t ws_bytes,
+                                  pint_stream_t stream) {
+  if (d < 1 || bw < 1 || boff < 0 || B < 0 || N < 0 || tile < 0 ||
+      (dtype != PINT_F64 && dtype != PINT_F32))
+    return PINT_ERR_INVALID_ARG;
+  if (B == 0 || N == 0) return PINT_OK;
+  if (!band || !b || !z) return PINT_ERR_INVALID_ARG;
+  return (pint_status)affine_scan_band(d, bw, boff, B, N, dtype, band, b, z0, z, tile, ws,
+                                       ws_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
 size_t pint_adjoint_workspace_bytes(const pint_system* sys, int64_t B, int64_t T, int64_t seg,
                                     int32_t dtype) {
   if (!sys || B < 0 || T < 0 || seg < 0) return 0;

@@ -56,6 +56,11 @@ size_t scan_ws_bytes(int d, int64_t B, int64_t N, int tile, int dtype);
 int affine_scan(int d, int64_t B, int64_t N, int dtype, const void* A, const void* b,
                 const void* z0, void* z, int tile, void* ws, size_t ws_bytes, hipStream_t s);
 
+size_t scan_band_ws_bytes(int d, int bw, int boff, int64_t B, int64_t N, int tile, int dtype);
+int affine_scan_band(int d, int bw, int boff, int64_t B, int64_t N, int dtype, const void* band,
+                     const void* b, const void* z0, void* z, int tile, void* ws, size_t ws_bytes,
+                     hipStream_t s);
+
 size_t adjoint_ws_bytes(int system, int d, int64_t B, int64_t T, int64_t seg, int dtype);
 int adjoint(const SolveArgs& a, const void* g, void* dL_dx0, void* dL_dth, int64_t seg);
 

@@ -719,6 +719,66 @@ __device__ __forceinline__ void block_matvec_g(const T* M, const T* c, T* z, T* 
   __syncthreads();
 }
 
+// The tile's exclusive prefix z_in, into sz, for a tile whose aggregate
+// (P, q) is in LDS (P with row stride PS, q in sq): publish the aggregate,
+// look back to the nearest predecessor whose inclusive prefix is known,
+// apply the aggregates in between, then publish this tile's inclusive prefix
+// P z_in + q.  Whole block (NT threads); st is a D-vector of LDS scratch.
+template <typename T, int D, int NT>
+__device__ void tile_prefix(const ScanArgs& a, int64_t seq, int64_t ts, const T* sP, int PS,
+                            const T* sq, T* sz, T* st) {
+  constexpr int E = D * D + D;
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  const int64_t base = seq * a.tiles_per_seq;
+  uint32_t* flags = a.flags + base;
+  T* aggp = static_cast<T*>(a.agg) + base * E;
+  T* inclp = static_cast<T*>(a.incl) + base * D;
+  __shared__ int64_t s_j;
+  if (ts == 0) {
+    for (int i = tid; i < D; i += NT) sz[i] = a.z0 ? static_cast<const T*>(a.z0)[seq * D + i] : T(0);
+    __syncthreads();
+  } else {
+    for (int idx = tid; idx < D * D; idx += NT) st_payload(aggp + ts * E + idx, sP[(idx / D) * PS + idx % D]);
+    for (int i = tid; i < D; i += NT) st_payload(aggp + ts * E + D * D + i, sq[i]);
+    __syncthreads();
+    if (tid == 0) publish_flag(flags + ts, FLAG_AGG);
+    if (wv == 0) {
+      // nearest predecessor whose inclusive prefix is known
+      int64_t end = ts - 1;
+      for (;;) {
+        uint32_t f;
+        const int k = lookback_window(flags, end, a.err, f);
+        if (k < PINT_WAVE) {
+          end -= k;
+          break;
+        }
+        end -= PINT_WAVE;
+      }
+      if (lane == 0) s_j = end;
+    }
+    __syncthreads();
+    const int64_t j = s_j;
+    for (int i = tid; i < D; i += NT) sz[i] = ld_payload(inclp + j * D + i);
+    __syncthreads();
+    // the aggregates in between, oldest first, as matrix-vector products
+    for (int64_t mm = j + 1; mm < ts; mm++)
+      block_matvec_g<T, D, NT>(aggp + mm * E, aggp + mm * E + D * D, sz, st, true);
+  }
+  // publish this tile's inclusive prefix: P z_in + q
+  {
+    constexpr int QC = (D * 2 <= NT) ? ((D * 4 <= NT) ? 4 : 2) : 1;
+    const int i = tid / QC, q = tid % QC;
+    T part = T(0);
+    if (i < D)
+      for (int k = 0; k < D / QC; k++) part += sP[i * PS + q * (D / QC) + k] * sz[q * (D / QC) + k];
+#pragma unroll
+    for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
+    if (i < D && q == 0) st_payload(inclp + ts * D + i, part + sq[i]);
+    __syncthreads();
+    if (tid == 0) publish_flag(flags + ts, FLAG_INCL);
+  }
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
   using SH = DenseScanShape<T, D>;
@@ -961,55 +1021,7 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
   }
   }  // generic fold
 
-  // lookback for z at the start of the tile
-  const int64_t base = seq * a.tiles_per_seq;
-  uint32_t* flags = a.flags + base;
-  T* aggp = static_cast<T*>(a.agg) + base * E;
-  T* inclp = static_cast<T*>(a.incl) + base * D;
-  __shared__ int64_t s_j;
-  if (ts == 0) {
-    for (int i = tid; i < D; i += NT) sz[i] = a.z0 ? static_cast<const T*>(a.z0)[seq * D + i] : T(0);
-    __syncthreads();
-  } else {
-    for (int idx = tid; idx < D * D; idx += NT) st_payload(aggp + ts * E + idx, sP[(idx / D) * PS + idx % D]);
-    for (int i = tid; i < D; i += NT) st_payload(aggp + ts * E + D * D + i, sq[i]);
-    __syncthreads();
-    if (tid == 0) publish_flag(flags + ts, FLAG_AGG);
-    if (wv == 0) {
-      // nearest predecessor whose inclusive prefix is known
-      int64_t end = ts - 1;
-      for (;;) {
-        uint32_t f;
-        const int k = lookback_window(flags, end, a.err, f);
-        if (k < PINT_WAVE) {
-          end -= k;
-          break;
-        }
-        end -= PINT_WAVE;
-      }
-      if (lane == 0) s_j = end;
-    }
-    __syncthreads();
-    const int64_t j = s_j;
-    for (int i = tid; i < D; i += NT) sz[i] = ld_payload(inclp + j * D + i);
-    __syncthreads();
-    // the aggregates in between, oldest first, as matrix-vector products
-    for (int64_t mm = j + 1; mm < ts; mm++)
-      block_matvec_g<T, D, NT>(aggp + mm * E, aggp + mm * E + D * D, sz, st, true);
-  }
-  // publish this tile's inclusive prefix: P z_in + q
-  {
-    constexpr int QC = (D * 2 <= NT) ? ((D * 4 <= NT) ? 4 : 2) : 1;
-    const int i = tid / QC, q = tid % QC;
-    T part = T(0);
-    if (i < D)
-      for (int k = 0; k < D / QC; k++) part += sP[i * PS + q * (D / QC) + k] * sz[q * (D / QC) + k];
-#pragma unroll
-    for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
-    if (i < D && q == 0) st_payload(inclp + ts * D + i, part + sq[i]);
-    __syncthreads();
-    if (tid == 0) publish_flag(flags + ts, FLAG_INCL);
-  }
+  tile_prefix<T, D, NT>(a, seq, ts, sP, PS, sq, sz, st);
 
   // outputs: z_{e0+m+1} = A_m z + b_m in order.  QC threads per row; each
   // thread's row segment of A_{m+1} and b_{m+1} are loaded during element m
@@ -1068,6 +1080,218 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
   }
 }
 
+// ------------------------------------------------------- banded scan ------
+//
+// Elements whose A is cyclically banded with BW diagonals,
+//   A(i, (i + k - BOFF) mod D) = band[i * BW + k]  for k < BW,
+// every other entry zero: the Jacobian of an RK4 step of a short-stencil
+// system, or its transpose in the adjoint.  An element is D*BW band values
+// (row-major) plus b.  The tile's running product fills in after a few
+// elements, so P stays dense; only the element is banded, and
+//   (A_m P)(i, c) = sum_k band_m[i][k] P((i + k - BOFF) mod D, c)
+// costs BW multiply-adds per entry on the vector units (instead of D, padded,
+// on matrix tiles).  The b-part rides along as column D of [P | q]: b_m
+// enters that column only.  Each wave owns RW rows of the product, its lanes
+// the D + 1 columns; a lane reads its column of the old product once per
+// element (WIN rows) and the band values are LDS broadcasts.
+//
+// Output pass: one wave walks the tile's elements, lane i holding row i of
+// the band in registers (a ring of the next PO elements' rows) and reading
+// z from an extended copy zx[j] = z[(j - BOFF) mod D], j < D + BW - 1, so its
+// BW operands are zx[i .. i+BW-1].
+template <typename T, int D, int BW, int BOFF>
+struct BandScanShape {
+  static constexpr int NT = 256, NW = NT / PINT_WAVE;
+  static constexpr int RW = (D + NW - 1) / NW;  // product rows per wave
+  static constexpr int NC = D + 1;              // columns: P and q
+  static constexpr int PSB = D + 1;             // LDS row stride of [P | q]
+  static constexpr int BWP = BW + 1;            // LDS row stride of a staged element: band row, b_i
+  static constexpr int NB = D * BW;             // band values per element
+  static constexpr int NPR = NB / 2;            // ... as pairs
+  static constexpr int NLD = (NPR + NT - 1) / NT;  // pair loads per thread per element
+  static constexpr int ZX = D + BW - 1;         // extended z
+  static constexpr int WIN = RW + BW - 1;       // rows of the old product one wave reads
+  static constexpr int PF = 4, PO = 4;          // ring depths (fold, output)
+  static_assert(NB % 2 == 0, "band values in pairs");
+  static_assert(NC <= PINT_WAVE, "a column per lane");
+  static_assert(D >= 2 * BW && BOFF < BW, "band must not wrap onto itself");
+};
+
+template <typename T, int D, int BW, int BOFF>
+__global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
+  using SH = BandScanShape<T, D, BW, BOFF>;
+  constexpr int NT = SH::NT, RW = SH::RW, NC = SH::NC, PSB = SH::PSB, BWP = SH::BWP;
+  constexpr int NB = SH::NB, NPR = SH::NPR, NLD = SH::NLD, ZX = SH::ZX, WIN = SH::WIN;
+  constexpr int PF = SH::PF, PO = SH::PO;
+  __shared__ T sPb[2][D * PSB];  // [P | q], ping-pong
+  __shared__ T sEl[2][D * BWP];  // staged elements, ping-pong
+  __shared__ T sq[D], sz[D], st[D];
+  __shared__ T zx[2][ZX];
+  __shared__ uint32_t s_tile;
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  if (tid == 0) s_tile = atomicAdd(a.counter, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t seq = tile % a.B, ts = tile / a.B;
+  const int64_t e0 = ts * (int64_t)a.L;
+  const int n_el = (int)((a.N - e0) < a.L ? (a.N - e0) : a.L);
+  const T* Bseq = static_cast<const T*>(a.A) + (seq * a.N + e0) * NB;
+  const T* bseq = static_cast<const T*>(a.b) + (seq * a.N + e0) * D;
+
+  typedef T v2_t __attribute__((ext_vector_type(2)));
+  const int bi = tid < D ? tid : 0;
+  // unconditional loads (the last pair / element again past the end), as
+  // in the dense scan: the ring's loads stay in flight across the loop
+  auto fetch = [&](int m, v2_t (&slot)[NLD], T& bv) {
+    const v2_t* src = reinterpret_cast<const v2_t*>(Bseq + (int64_t)m * NB);
+#pragma unroll
+    for (int j = 0; j < NLD; j++) slot[j] = src[min(j * NT + tid, NPR - 1)];
+    bv = bseq[(int64_t)m * D + bi];
+  };
+  auto stage = [&](const v2_t (&slot)[NLD], T bv, T* el) {
+#pragma unroll
+    for (int j = 0; j < NLD; j++) {
+      const int pr = j * NT + tid;
+      if (pr < NPR) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int f = 2 * pr + h, i = f / BW, k = f % BW;
+          el[i * BWP + k] = slot[j][h];
+        }
+      }
+    }
+    if (tid < D) el[tid * BWP + BW] = bv;
+  };
+
+  // ---- prologue: elements 0 and 1 staged, P <- A_0 (dense), q <- b_0 ----
+  v2_t ring[PF][NLD];
+  T rb[PF];
+  {
+    v2_t s0[NLD], s1[NLD];
+    T b0, b1;
+    fetch(0, s0, b0);
+    fetch(min(1, n_el - 1), s1, b1);
+#pragma unroll
+    for (int u = 0; u < PF; u++) fetch(min(2 + u, n_el - 1), ring[u], rb[u]);
+    stage(s0, b0, sEl[0]);
+    stage(s1, b1, sEl[1]);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < D * PSB; idx += NT) {
+    const int r = idx / PSB, c = idx % PSB;
+    T v = T(0);
+    if (c == D) {
+      v = sEl[0][r * BWP + BW];
+    } else {
+      int k = c - r + BOFF;
+      k = k < 0 ? k + D : (k >= D ? k - D : k);
+      if (k < BW) v = sEl[0][r * BWP + k];
+    }
+    sPb[0][idx] = v;
+  }
+  // every load complete at the loop entry (see the dense scan's fold)
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  __syncthreads();
+
+  // ---- fold: step m computes P_m = A_m P_{m-1} (element m staged in step
+  // m-1) and stages element m+1; one barrier per step ----
+  const int r0 = wv * RW;
+  auto fold_one = [&](const int m, v2_t (&slot)[NLD], T& bslot) __attribute__((always_inline)) {
+    stage(slot, bslot, sEl[(m + 1) & 1]);  // last read in step m-1
+    fetch(min(m + 1 + PF, n_el - 1), slot, bslot);
+    const T* el = sEl[m & 1];
+    const T* Po = sPb[(m - 1) & 1];
+    T* Pn = sPb[m & 1];
+    if (lane < NC && r0 < D) {
+      T pc[WIN];
+#pragma unroll
+      for (int w = 0; w < WIN; w++) {
+        int row = r0 - BOFF + w;
+        row = row < 0 ? row + D : (row >= D ? row - D : row);
+        pc[w] = Po[row * PSB + lane];
+      }
+#pragma unroll
+      for (int rr = 0; rr < RW; rr++) {
+        const int r = r0 + rr;
+        if (D % SH::NW == 0 || r < D) {
+          T acc0 = lane == D ? el[r * BWP + BW] : T(0), acc1 = T(0);
+#pragma unroll
+          for (int k = 0; k + 1 < BW; k += 2) {
+            acc0 += el[r * BWP + k] * pc[rr + k];
+            acc1 += el[r * BWP + k + 1] * pc[rr + k + 1];
+          }
+          if (BW & 1) acc0 += el[r * BWP + BW - 1] * pc[rr + BW - 1];
+          Pn[r * PSB + lane] = acc0 + acc1;
+        }
+      }
+    }
+    lds_barrier();
+  };
+  int m0 = 1;  // whole groups of PF steps, then the rest
+  for (; m0 + PF <= n_el; m0 += PF)
+#pragma unroll
+    for (int u = 0; u < PF; u++) fold_one(m0 + u, ring[u], rb[u]);
+#pragma unroll
+  for (int u = 0; u + 1 < PF; u++)
+    if (m0 + u < n_el) fold_one(m0 + u, ring[u], rb[u]);
+  const T* Pf = sPb[(n_el - 1) & 1];
+  for (int i = tid; i < D; i += NT) sq[i] = Pf[i * PSB + D];
+  __syncthreads();
+
+  tile_prefix<T, D, NT>(a, seq, ts, Pf, PSB, sq, sz, st);
+
+  // ---- outputs: z_{e0+m+1} = A_m z + b_m, one wave ----
+  if (wv != 0) return;  // no block barrier follows
+  T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
+  const bool act = lane < D;
+  const int i = act ? lane : 0;
+  auto put = [&](T* zb, T v) {
+    zb[i + BOFF] = v;
+    if (i + BOFF >= D) zb[i + BOFF - D] = v;
+    if (i + BOFF + D < ZX) zb[i + BOFF + D] = v;
+  };
+  if (act) put(zx[0], sz[i]);
+  T row[PO][BW], rbo[PO];
+  auto fetch_row = [&](int m, T (&rw)[BW], T& bv) {
+    const T* src = Bseq + (int64_t)m * NB + i * BW;
+#pragma unroll
+    for (int k = 0; k < BW; k++) rw[k] = src[k];
+    bv = bseq[(int64_t)m * D + i];
+  };
+#pragma unroll
+  for (int u = 0; u < PO; u++) fetch_row(min(u, n_el - 1), row[u], rbo[u]);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): as in the fold
+  __builtin_amdgcn_wave_barrier();
+  auto out_one = [&](const int m, T (&rw)[BW], T& bv) __attribute__((always_inline)) {
+    const T* zc = zx[m & 1];
+    T* zn = zx[(m + 1) & 1];
+    T acc0 = bv, acc1 = T(0);
+#pragma unroll
+    for (int k = 0; k + 1 < BW; k += 2) {
+      acc0 += rw[k] * zc[i + k];
+      acc1 += rw[k + 1] * zc[i + k + 1];
+    }
+    if (BW & 1) acc0 += rw[BW - 1] * zc[i + BW - 1];
+    const T zv = acc0 + acc1;
+    fetch_row(min(m + PO, n_el - 1), rw, bv);
+    if (act) {
+      put(zn, zv);
+      zg[(int64_t)m * D + i] = zv;
+    }
+    // the wave's LDS operations complete in order: the next element's reads
+    // see these writes; keep the compiler from moving them across
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+  };
+  m0 = 0;
+  for (; m0 + PO <= n_el; m0 += PO)
+#pragma unroll
+    for (int u = 0; u < PO; u++) out_one(m0 + u, row[u], rbo[u]);
+#pragma unroll
+  for (int u = 0; u + 1 < PO; u++)
+    if (m0 + u < n_el) out_one(m0 + u, row[u], rbo[u]);
+}
+
 // ------------------------------------------------------------- host -------
 
 static int scan_tile_elems(int d, int dtype, int tile) {
@@ -1091,7 +1315,8 @@ static int scan_tile_elems(int d, int dtype, int tile) {
 // chain of inclusive prefixes between tiles stays short.
 static int dense_tile_len(int64_t B, int64_t N) {
   int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const int64_t per_seq_tiles = (cus + B - 1) / B;
   int64_t L = (N + per_seq_tiles - 1) / per_seq_tiles;
   if (L < 1) L = 1;
@@ -1189,6 +1414,77 @@ int affine_scan(int d, int64_t B, int64_t N, int dtype, const void* A, const voi
 #undef PINT_CASE_SMALL
 #undef PINT_CASE_DENSE
   return ST_UNSUPPORTED;
+}
+
+
+// ------------------------------------------------------------ banded ------
+
+// Band shapes compiled: d = 40 with 13 diagonals, offset 8 (the RK4 Jacobian
+// of Lorenz-96) or 4 (its transpose).
+static bool scan_band_shape(int d, int bw, int boff) {
+  return d == 40 && bw == 13 && (boff == 4 || boff == 8);
+}
+
+// Band default tile length: about four tiles per compute unit, so the output
+// pass of one tile (a single wave) overlaps the folds of the others.
+static int band_tile_len(int64_t B, int64_t N) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t per_seq_tiles = (4 * (int64_t)cus + B - 1) / B;
+  int64_t L = (N + per_seq_tiles - 1) / per_seq_tiles;
+  if (L < 16) L = 16;
+  if (L > (1 << 20)) L = 1 << 20;
+  return (int)L;
+}
+
+size_t scan_band_ws_bytes(int d, int bw, int boff, int64_t B, int64_t N, int tile, int dtype) {
+  if (!scan_band_shape(d, bw, boff) || B < 0 || N < 0 || tile < 0) return 0;
+  const int L = tile > 0 ? tile : band_tile_len(B, N);
+  const int64_t nt = B * ((N + L - 1) / L);
+  const size_t s = dtype == 0 ? 8 : 4;
+  return 256 + align_up((size_t)nt * 4) + align_up((size_t)nt * (d * d + d) * s) +
+         align_up((size_t)nt * d * s);
+}
+
+template <typename T, int BOFF>
+static int launch_band(const ScanArgs& sa, int64_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_scan_band<T, 40, 13, BOFF>), dim3((unsigned)grid), dim3(256), 0, s, sa);
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
+}
+
+int affine_scan_band(int d, int bw, int boff, int64_t B, int64_t N, int dtype, const void* band,
+                     const void* b, const void* z0, void* z, int tile, void* ws, size_t ws_bytes,
+                     hipStream_t s) {
+  if (!scan_band_shape(d, bw, boff)) return ST_UNSUPPORTED;
+  if ((dtype != 0 && dtype != 1) || tile < 0) return ST_INVALID;
+  const size_t sz = dtype == 0 ? 8 : 4;
+  // the band is read in pairs of values
+  if (reinterpret_cast<uintptr_t>(band) % (2 * sz) != 0) return ST_INVALID;
+  const size_t need = scan_band_ws_bytes(d, bw, boff, B, N, tile, dtype);
+  if (!ws || ws_bytes < need) return ST_WORKSPACE;
+  const int L = tile > 0 ? tile : band_tile_len(B, N);
+  const int64_t tps = (N + L - 1) / L;
+  const int64_t nt = B * tps;
+  if (nt > 0x7fffffffLL) return ST_INVALID;
+  char* w = static_cast<char*>(ws);
+  ScanArgs sa{};
+  sa.B = B;
+  sa.N = N;
+  sa.tiles_per_seq = tps;
+  sa.L = L;
+  sa.A = band;
+  sa.b = b;
+  sa.z0 = z0;
+  sa.z = z;
+  sa.counter = reinterpret_cast<uint32_t*>(w);
+  sa.err = reinterpret_cast<uint32_t*>(w) + 1;
+  sa.flags = reinterpret_cast<uint32_t*>(w + 256);
+  sa.agg = w + 256 + align_up((size_t)nt * 4);
+  sa.incl = w + 256 + align_up((size_t)nt * 4) + align_up((size_t)nt * (d * d + d) * sz);
+  if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w), 64 + (size_t)nt, 0u, s)) return rc;
+  if (boff == 4) return dtype == 0 ? launch_band<double, 4>(sa, nt, s) : launch_band<float, 4>(sa, nt, s);
+  return dtype == 0 ? launch_band<double, 8>(sa, nt, s) : launch_band<float, 8>(sa, nt, s);
 }
 
 }  // namespace pint

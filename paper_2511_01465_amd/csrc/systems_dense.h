@@ -121,6 +121,24 @@ struct DSysL96 {
       if (kb < BW) band[kb * D + i] = col[k];
     }
   }
+
+  // The transpose of the band, row-major: J^T(j, i) = J(i, j) is row j of
+  // J^T, whose nonzero entries sit at columns (j + k' - BOFFT) mod D with
+  // k' = BW - 1 - kb, BOFFT = BW - 1 - BOFF; stored at bandT[j * BW + k'].
+  // The QB threads of column j of J fill row j of J^T (every k' once).
+  static constexpr int BOFFT = BW - 1 - BOFF;
+  __device__ static void jac_bandT_thread(const Stage* st, const T*, int sub, T dt, T* bandT) {
+    T col[RB];
+    jac_column(st, sub, dt, col);
+    const int j = sub / QB, r0 = (sub % QB) * RB;
+#pragma unroll
+    for (int k = 0; k < RB; k++) {
+      const int i = r0 + k;
+      int kb = j - i + BOFF;
+      kb = kb < 0 ? kb + D : (kb >= D ? kb - D : kb);
+      if (kb < BW) bandT[j * BW + (BW - 1 - kb)] = col[k];
+    }
+  }
 };
 
 // ------------------------------------------------------------- Kuramoto --

@@ -93,3 +93,68 @@ def test_empty_and_errors(pint):
     b = torch.zeros((1, 4, 9), dtype=torch.float64, device=DEV)
     with pytest.raises(pint.PintError):
         pint.affine_scan(A, b)
+
+
+# ------------------------------------------------------------ banded scan --
+
+def _check_band(pint, orc, N, B, boff, dtype, with_z0, seed, tile=0):
+    d, bw = 40, 13
+    A = np.empty((B, N, d, d))
+    band = np.empty((B, N, d, bw))
+    b = np.empty((B, N, d))
+    for s in range(B):
+        A[s], band[s], b[s] = W.random_band_affine(N, d, bw, boff, seed=seed + s)
+    z0 = np.random.default_rng(seed).normal(size=(B, d)) if with_z0 else None
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    bandt, bt = torch.tensor(band, dtype=tdt, device=DEV), torch.tensor(b, dtype=tdt, device=DEV)
+    z0t = None if z0 is None else torch.tensor(z0, dtype=tdt, device=DEV)
+    z = pint.affine_scan_band(bandt, bt, boff, z0t, tile=tile)
+    torch.cuda.synchronize()
+    if dtype == "f32":
+        A, b = A.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)
+        z0 = None if z0 is None else z0.astype(np.float32).astype(np.float64)
+    ref = _ref(orc, A, b, z0)
+    got = z.double().cpu().numpy()
+    scale = max(1.0, np.abs(ref).max())
+    err = np.abs(got - ref).max() / scale
+    assert err <= (1e-11 if dtype == "f64" else 1e-4), (N, B, boff, dtype, tile, err)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("boff", [4, 8])
+def test_band_several_tiles_ragged(pint, orc, boff, dtype):
+    """Banded elements (d = 40, 13 diagonals) against the oracle's recursion on
+    the same elements expanded to dense: several tiles, a ragged tail, a
+    starting vector."""
+    print(f"[scan-band] boff={boff} {dtype}", flush=True)
+    _check_band(pint, orc, 5 * 64 + 13, 3, boff, dtype, True, seed=60 + boff, tile=64)
+
+
+@pytest.mark.parametrize("N,tile", [(1, 0), (2, 0), (5, 1), (17, 16), (700, 0), (2048, 0)])
+def test_band_lengths_and_tiles(pint, orc, N, tile):
+    print(f"[scan-band] N={N} tile={tile}", flush=True)
+    _check_band(pint, orc, N, 2, 4, "f64", N % 2 == 0, seed=70, tile=tile)
+
+
+def test_band_many_sequences(pint, orc):
+    """More tiles than resident workgroups: 64 sequences of 1500 elements at
+    the default tile length."""
+    _check_band(pint, orc, 1500, 64, 4, "f64", True, seed=80)
+
+
+def test_band_errors(pint):
+    band = torch.zeros((1, 4, 40, 12), dtype=torch.float64, device=DEV)  # 12 diagonals: not built
+    b = torch.zeros((1, 4, 40), dtype=torch.float64, device=DEV)
+    with pytest.raises(pint.PintError):
+        pint.affine_scan_band(band, b, 4)
+    band = torch.zeros((1, 4, 40, 13), dtype=torch.float64, device=DEV)
+    with pytest.raises(pint.PintError):
+        pint.affine_scan_band(band, b, 5)  # offset 5: not built
+    flat = torch.zeros(4 * 40 * 13 + 1, dtype=torch.float64, device=DEV)
+    mis = flat[1:].view(1, 4, 40, 13)       # 8-byte aligned only
+    z = torch.empty((1, 4, 40), dtype=torch.float64, device=DEV)
+    ws = torch.empty(pint.pint_scan_band_workspace_bytes(40, 13, 4, 1, 4, 0, pint.F64),
+                     dtype=torch.uint8, device=DEV)
+    assert pint.pint_affine_scan_band(40, 13, 4, 1, 4, pint.F64, mis, b, None, z, 0, ws) == \
+        pint.ERR_INVALID_ARG
+    assert pint.affine_scan_band(band[:, :0].contiguous(), b[:, :0].contiguous(), 4).shape == (1, 0, 40)

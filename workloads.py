@@ -127,6 +127,32 @@ def random_affine(N: int, d: int, seed: int = 0, kind: str = "rotation"):
     return A, b
 
 
+def random_band_affine(N: int, d: int, bw: int, boff: int, seed: int = 0):
+    """Cyclically banded orthogonal elements for the banded scan: A_n is the
+    product of four layers of cyclic nearest-neighbour Givens rotations
+    (pairs (0,1),(2,3),.. then (1,2),..,(d-1,0), twice; d even), so its
+    nonzeros lie within offsets [-4, 4] of the diagonal, inside the band
+    j - i in [-boff, bw - 1 - boff] (mod d) when boff >= 4 and
+    bw - 1 - boff >= 4.  Returns (A [N,d,d] dense, band [N,d,bw] with
+    A(i, (i + k - boff) mod d) = band[i, k], b [N,d])."""
+    assert d % 2 == 0 and boff >= 4 and bw - 1 - boff >= 4
+    r = _rng(seed)
+    A = np.zeros((N, d, d))
+    A[:] = np.eye(d)
+    for layer in range(4):
+        for p in range(layer % 2, d, 2):
+            q = (p + 1) % d
+            th = r.uniform(0.0, 2.0 * math.pi, size=N)
+            c, s = np.cos(th), np.sin(th)
+            rp, rq = A[:, p, :].copy(), A[:, q, :].copy()
+            A[:, p, :] = c[:, None] * rp - s[:, None] * rq
+            A[:, q, :] = s[:, None] * rp + c[:, None] * rq
+    idx = (np.arange(d)[:, None] + np.arange(bw)[None, :] - boff) % d   # [d, bw] columns
+    band = np.take_along_axis(A, np.broadcast_to(idx, (N, d, bw)), axis=2)
+    b = r.normal(0.0, 1.0, size=(N, d))
+    return A, band, b
+
+
 def paper_pins():
     """The three explicit problems of the paper's Sec. 4.1 at dt = 1e-2 with
     the paper's initial guesses (ones, ones, zeros)."""
