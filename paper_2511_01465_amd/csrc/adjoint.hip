@@ -136,6 +136,65 @@ __global__ __launch_bounds__(S::NT) void k_adj_elems_dense(AdjArgs a) {
   }
 }
 
+// Banded systems: the transposed band of each step, one thread per column
+// of J (row of J^T) computing only the band (S::jac_band_column), BNT / D
+// steps per workgroup; the stage points by one wave per step as above.
+template <typename T, class S>
+__global__ __launch_bounds__(256) void k_adj_elems_band(AdjArgs a) {
+  constexpr int D = S::D, NP = S::NP, BW = S::BW, NT = 256, NW = NT / PINT_WAVE;
+  constexpr int SPP = NT / D;  // steps per workgroup
+  __shared__ typename S::Stage s_stage[SPP];
+  __shared__ T s_P[SPP][NP];
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  const int64_t L = a.i_hi - a.i_lo, total = a.B * L;
+  const int64_t g0 = (int64_t)blockIdx.x * SPP;
+  for (int sl = 0; sl < SPP; sl++) {
+    const int64_t gi = g0 + sl;
+    if (gi < total) {
+      const T* P = static_cast<const T*>(a.params) + (gi / L) * a.pstride;
+      for (int r = tid; r < NP; r += NT) s_P[sl][r] = P[r];
+    }
+  }
+  __syncthreads();
+  for (int sl = wv; sl < SPP; sl += NW) {
+    const int64_t gi = g0 + sl;
+    if (gi >= total) continue;
+    const int64_t inst = gi / L, i = a.i_lo + gi % L;
+    const T* G = static_cast<const T*>(a.g) + inst * a.T * D;
+    T* bo = static_cast<T*>(a.b) + gi * D;
+    const int64_t n = adj_state(a.T, i);
+    if (i == 0) {
+      for (int r = lane; r < D; r += PINT_WAVE) bo[r] = G[(a.T - 1) * D + r];
+      continue;
+    }
+    for (int r = lane; r < D; r += PINT_WAVE) bo[r] = (i == a.T) ? T(0) : G[(n - 1) * D + r];
+    const T* X = static_cast<const T*>(a.traj) + inst * a.T * D;
+    const T* x0 = static_cast<const T*>(a.x0) + inst * D;
+    T xp[S::R], phi[S::R];
+#pragma unroll
+    for (int r = 0; r < S::R; r++) {
+      const int c = lane + 64 * r;
+      xp[r] = c < D ? (n == 0 ? x0[c] : X[(n - 1) * D + c]) : T(0);
+    }
+    wave_rk4<T, S>(s_P[sl], (T)a.dt, xp, phi, &s_stage[sl], lane);
+  }
+  __syncthreads();
+  const int sl = tid / D, j = tid % D;
+  const int64_t gi = g0 + sl;
+  if (sl >= SPP || gi >= total) return;
+  const int64_t i = a.i_lo + gi % L;
+  T* row = static_cast<T*>(a.A) + gi * D * BW + (int64_t)j * BW;
+  T col[BW];
+  if (i == 0) {  // identity (multiplies z_0 = 0): the diagonal is band column BOFFT
+#pragma unroll
+    for (int r = 0; r < BW; r++) col[r] = (r == S::BOFFT) ? T(1) : T(0);
+  } else {
+    S::jac_band_column(&s_stage[sl], j, (T)a.dt, col);
+  }
+#pragma unroll
+  for (int r = 0; r < BW; r++) row[r] = col[r];
+}
+
 // Copy this segment's scan outputs into lambda [B][T+1][D] and keep the
 // last one as the next segment's starting vector.
 template <typename T>
@@ -181,40 +240,48 @@ __global__ void k_adj_theta_small(AdjArgs a, const T* lam, T* dth) {
 
 // Lorenz-96: theta = F, S = dPhi/dF by the chain rule through the stages
 // (f_F = 1):  D1 = 1, D_s = Jf(x_s)(c D_{s-1}) + 1, S = dt/6 (D1+2D2+2D3+D4).
-// One wave per step; the stencil product by shuffles.
+// One wave per run of TH_SPW consecutive steps of one instance (the stencil
+// product by shuffles), the run's terms summed in registers and added to
+// dL/dF with one atomic per wave.
+constexpr int TH_SPW = 64;
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_adj_theta_l96(AdjArgs a, const T* lam, T* dth) {
   using S = DSysL96<T, DIM>;
   constexpr int D = DIM;
-  const int lane = threadIdx.x % 64;
-  const int64_t gi = blockIdx.x * 4 + threadIdx.x / 64;
-  if (gi >= a.B * a.T) return;
-  const int64_t inst = gi / a.T, n = gi % a.T + 1;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int64_t per_inst = (a.T + 4 * TH_SPW - 1) / (4 * TH_SPW);  // blocks per instance
+  const int64_t inst = blockIdx.x / per_inst;
+  const int64_t n0 = (blockIdx.x % per_inst) * 4 * TH_SPW + (int64_t)wv * TH_SPW + 1;
+  if (inst >= a.B || n0 > a.T) return;
+  const int64_t n1 = n0 + TH_SPW - 1 < a.T ? n0 + TH_SPW - 1 : a.T;
   const T* X = static_cast<const T*>(a.traj) + inst * a.T * D;
   const T* x0 = static_cast<const T*>(a.x0) + inst * D;
   const T* P = static_cast<const T*>(a.params) + inst * a.pstride;
   const int i = lane < D ? lane : 0;
   const T dt = (T)a.dt, h2 = T(0.5) * dt, c6 = dt / T(6);
-  T x[1] = {lane < D ? (n == 1 ? x0[i] : X[(n - 2) * D + i]) : T(0)};
-  T k[1], y[1] = {x[0]};
-  T Dv = T(1), acc = T(1);
-  S::f(P, x, k, lane);
-  for (int s = 1; s < 4; s++) {
-    const T cprev = (s == 3) ? dt : h2;   // x_{s+1} = x + c k_s
-    y[0] = x[0] + cprev * k[0];
-    // Jf(y) (cprev * Dv) + 1
-    const T v = cprev * Dv;
-    const T yp1 = __shfl(y[0], (i + 1) % D, 64), ym1 = __shfl(y[0], (i + D - 1) % D, 64);
-    const T ym2 = __shfl(y[0], (i + D - 2) % D, 64);
-    const T vp1 = __shfl(v, (i + 1) % D, 64), vm1 = __shfl(v, (i + D - 1) % D, 64);
-    const T vm2 = __shfl(v, (i + D - 2) % D, 64);
-    Dv = ym1 * (vp1 - vm2) + (yp1 - ym2) * vm1 - v + T(1);
-    acc += ((s == 3) ? T(1) : T(2)) * Dv;
-    S::f(P, y, k, lane);
+  T part = T(0);
+  for (int64_t n = n0; n <= n1; n++) {
+    T x[1] = {lane < D ? (n == 1 ? x0[i] : X[(n - 2) * D + i]) : T(0)};
+    T k[1], y[1] = {x[0]};
+    T Dv = T(1), acc = T(1);
+    S::f(P, x, k, lane);
+    for (int s = 1; s < 4; s++) {
+      const T cprev = (s == 3) ? dt : h2;  // x_{s+1} = x + c k_s
+      y[0] = x[0] + cprev * k[0];
+      // Jf(y) (cprev * Dv) + 1
+      const T v = cprev * Dv;
+      const T yp1 = __shfl(y[0], (i + 1) % D, 64), ym1 = __shfl(y[0], (i + D - 1) % D, 64);
+      const T ym2 = __shfl(y[0], (i + D - 2) % D, 64);
+      const T vp1 = __shfl(v, (i + 1) % D, 64), vm1 = __shfl(v, (i + D - 1) % D, 64);
+      const T vm2 = __shfl(v, (i + D - 2) % D, 64);
+      Dv = ym1 * (vp1 - vm2) + (yp1 - ym2) * vm1 - v + T(1);
+      acc += ((s == 3) ? T(1) : T(2)) * Dv;
+      S::f(P, y, k, lane);
+    }
+    const T* ln = lam + (inst * (a.T + 1) + (a.T - n)) * D;
+    if (lane < D) part += c6 * acc * ln[i];
   }
-  const T Sv = c6 * acc;
-  const T* ln = lam + (inst * (a.T + 1) + (a.T - n)) * D;
-  T part = lane < D ? Sv * ln[i] : T(0);
   part = wave_sum(part);
   if (lane == 0) atomicAdd(dth + inst, part);
 }
@@ -335,6 +402,10 @@ int adjoint(const SolveArgs& sa, const void* g, void* dL_dx0, void* dL_dth, int6
       if constexpr (decltype(is_small)::value) {
         const int grid = (int)((tot + 255) / 256 < 8192 ? (tot + 255) / 256 : 8192);
         hipLaunchKernelGGL((k_adj_elems_small<T_, S>), dim3(grid), dim3(256), 0, st, a);
+      } else if constexpr (S::BANDED) {
+        constexpr int spp = 256 / D;
+        const int64_t grid = (tot + spp - 1) / spp;
+        hipLaunchKernelGGL((k_adj_elems_band<T_, S>), dim3((unsigned)grid), dim3(256), 0, st, a);
       } else {
         const int64_t grid = (tot + S::SPP - 1) / S::SPP;
         hipLaunchKernelGGL((k_adj_elems_dense<T_, S>), dim3((unsigned)grid), dim3(S::NT), 0, st, a);
@@ -380,8 +451,9 @@ int adjoint(const SolveArgs& sa, const void* g, void* dL_dx0, void* dL_dth, int6
                              (const T_*)lam, static_cast<T_*>(dL_dth));
       } else if constexpr (D == 40 && S::NP == 1) {
         const int64_t tot = B * T;
+        const int64_t per_inst = (T + 4 * TH_SPW - 1) / (4 * TH_SPW);
         if (tot > 0)
-          hipLaunchKernelGGL((k_adj_theta_l96<T_, 40>), dim3((unsigned)((tot + 3) / 4)), dim3(256), 0,
+          hipLaunchKernelGGL((k_adj_theta_l96<T_, 40>), dim3((unsigned)(B * per_inst)), dim3(256), 0,
                              st, a, (const T_*)lam, static_cast<T_*>(dL_dth));
       } else {
         return ST_UNSUPPORTED;

@@ -122,6 +122,54 @@ struct DSysL96 {
     }
   }
 
+  // Column j of J restricted to its band, by one thread: the tangent of
+  // e_j through the four stages reaches rows j-1..j+2 after the first stage
+  // product, and one row down / two rows up per further stage (the stencil
+  // reads u_{i+1}, u_{i-2}, u_{i-1}, u_i), so it lives in rows
+  // j-4 .. j+8 = j - BOFFT + r, r < BW, throughout; everything outside is
+  // exactly zero.  col[r] = J(j - BOFFT + r, j), which is also row j of J^T
+  // at band index r (offset BOFFT).
+  __device__ static void jac_band_column(const Stage* st, int j, T dt, T (&col)[BW]) {
+    static_assert(BW - 1 - BOFF == 4 && BOFF == 8, "stencil reach of the RK4 Jacobian");
+    constexpr int LO = BW - 1 - BOFF;   // rows start at j - LO
+    constexpr int YW = BW + 3;          // stage values read: rows j-LO-2 .. j-LO+BW
+    int yi[YW];
+#pragma unroll
+    for (int w = 0; w < YW; w++) {
+      int g = j - LO - 2 + w;
+      g = g < 0 ? g + D : (g >= D ? g - D : g);
+      yi[w] = g;
+    }
+    const T h2 = T(0.5) * dt, c6 = dt / T(6);
+    T u[BW], acc[BW];
+#pragma unroll
+    for (int r = 0; r < BW; r++) u[r] = (r == LO) ? T(1) : T(0);
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      const T* x = st->x[s];
+      T y[YW];
+#pragma unroll
+      for (int w = 0; w < YW; w++) y[w] = x[yi[w]];
+      const T w_s = (s == 0 || s == 3) ? T(1) : T(2);
+      const T c = (s == 2) ? dt : h2;
+      T un[BW];
+#pragma unroll
+      for (int r = 0; r < BW; r++) {
+        // row i = j - LO + r: y_{i-1} = y[r+1], y_{i+1} = y[r+3], y_{i-2} = y[r]
+        const T up1 = r + 1 < BW ? u[r + 1] : T(0);
+        const T um1 = r >= 1 ? u[r - 1] : T(0);
+        const T um2 = r >= 2 ? u[r - 2] : T(0);
+        const T K = y[r + 1] * (up1 - um2) + (y[r + 3] - y[r]) * um1 - u[r];
+        acc[r] = (s == 0) ? K : acc[r] + w_s * K;
+        un[r] = ((r == LO) ? T(1) : T(0)) + c * K;
+      }
+#pragma unroll
+      for (int r = 0; r < BW; r++) u[r] = un[r];
+    }
+#pragma unroll
+    for (int r = 0; r < BW; r++) col[r] = ((r == LO) ? T(1) : T(0)) + c6 * acc[r];
+  }
+
   // The transpose of the band, row-major: J^T(j, i) = J(i, j) is row j of
   // J^T, whose nonzero entries sit at columns (j + k' - BOFFT) mod D with
   // k' = BW - 1 - kb, BOFFT = BW - 1 - BOFF; stored at bandT[j * BW + k'].
