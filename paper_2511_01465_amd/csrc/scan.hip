@@ -804,6 +804,12 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
   const T* Aseq = static_cast<const T*>(a.A) + (seq * a.N + e0) * D * D;
   const T* bseq = static_cast<const T*>(a.b) + (seq * a.N + e0) * D;
 
+  // One tile per sequence: it starts from z0 and has no successor, so its
+  // aggregate is never used; straight to the outputs.
+  if (a.tiles_per_seq == 1) {
+    for (int i = tid; i < D; i += NT) sz[i] = a.z0 ? static_cast<const T*>(a.z0)[seq * D + i] : T(0);
+    __syncthreads();
+  } else {
   if constexpr (SH::STAT) {
     // ---- stationary product: P in accumulators, A_m staged through LDS ----
     // AUG (D < DP): the element is staged as the augmented matrix
@@ -1022,6 +1028,7 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
   }  // generic fold
 
   tile_prefix<T, D, NT>(a, seq, ts, sP, PS, sq, sz, st);
+  }  // tiles_per_seq > 1
 
   // outputs: z_{e0+m+1} = A_m z + b_m in order.  QC threads per row; each
   // thread's row segment of A_{m+1} and b_{m+1} are loaded during element m
@@ -1093,19 +1100,22 @@ __global__ __launch_bounds__(256) void k_scan_dense(ScanArgs a) {
 // on matrix tiles).  The b-part rides along as column D of [P | q]: b_m
 // enters that column only.  Each wave owns RW rows of the product, its lanes
 // the D + 1 columns; a lane reads its column of the old product once per
-// element (WIN rows) and the band values are LDS broadcasts.
+// element (WIN rows).  The element is staged diagonal-major, so for each
+// diagonal k the RW band values of the wave's rows are one contiguous LDS
+// broadcast feeding RW independent accumulators.
 //
-// Output pass: one wave walks the tile's elements, lane i holding row i of
-// the band in registers (a ring of the next PO elements' rows) and reading
-// z from an extended copy zx[j] = z[(j - BOFF) mod D], j < D + BW - 1, so its
-// BW operands are zx[i .. i+BW-1].
+// Output pass (k_scan_band_out): one wave per tile walks the tile's
+// elements, lane i holding row i of the band in registers (a ring of the
+// next PO elements' rows) and reading z from an extended copy
+// zx[j] = z[(j - BOFF) mod D], j < D + BW - 1, so its BW operands are
+// zx[i .. i+BW-1].
 template <typename T, int D, int BW, int BOFF>
 struct BandScanShape {
   static constexpr int NT = 256, NW = NT / PINT_WAVE;
   static constexpr int RW = (D + NW - 1) / NW;  // product rows per wave
   static constexpr int NC = D + 1;              // columns: P and q
   static constexpr int PSB = D + 1;             // LDS row stride of [P | q]
-  static constexpr int BWP = BW + 1;            // LDS row stride of a staged element: band row, b_i
+  static constexpr int EL = (BW + 1) * D;        // staged element: band[k][i] (k-major), then b
   static constexpr int NB = D * BW;             // band values per element
   static constexpr int NPR = NB / 2;            // ... as pairs
   static constexpr int NLD = (NPR + NT - 1) / NT;  // pair loads per thread per element
@@ -1120,13 +1130,11 @@ struct BandScanShape {
 template <typename T, int D, int BW, int BOFF>
 __global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
   using SH = BandScanShape<T, D, BW, BOFF>;
-  constexpr int NT = SH::NT, RW = SH::RW, NC = SH::NC, PSB = SH::PSB, BWP = SH::BWP;
-  constexpr int NB = SH::NB, NPR = SH::NPR, NLD = SH::NLD, ZX = SH::ZX, WIN = SH::WIN;
-  constexpr int PF = SH::PF, PO = SH::PO;
+  constexpr int NT = SH::NT, RW = SH::RW, NC = SH::NC, PSB = SH::PSB, EL = SH::EL;
+  constexpr int NB = SH::NB, NPR = SH::NPR, NLD = SH::NLD, WIN = SH::WIN, PF = SH::PF;
   __shared__ T sPb[2][D * PSB];  // [P | q], ping-pong
-  __shared__ T sEl[2][D * BWP];  // staged elements, ping-pong
+  __shared__ T sEl[2][EL];       // staged elements, ping-pong
   __shared__ T sq[D], sz[D], st[D];
-  __shared__ T zx[2][ZX];
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
   if (tid == 0) s_tile = atomicAdd(a.counter, 1u);
@@ -1156,11 +1164,11 @@ __global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
 #pragma unroll
         for (int h = 0; h < 2; h++) {
           const int f = 2 * pr + h, i = f / BW, k = f % BW;
-          el[i * BWP + k] = slot[j][h];
+          el[k * D + i] = slot[j][h];
         }
       }
     }
-    if (tid < D) el[tid * BWP + BW] = bv;
+    if (tid < D) el[BW * D + tid] = bv;
   };
 
   // ---- prologue: elements 0 and 1 staged, P <- A_0 (dense), q <- b_0 ----
@@ -1181,11 +1189,11 @@ __global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
     const int r = idx / PSB, c = idx % PSB;
     T v = T(0);
     if (c == D) {
-      v = sEl[0][r * BWP + BW];
+      v = sEl[0][BW * D + r];
     } else {
       int k = c - r + BOFF;
       k = k < 0 ? k + D : (k >= D ? k - D : k);
-      if (k < BW) v = sEl[0][r * BWP + k];
+      if (k < BW) v = sEl[0][k * D + r];
     }
     sPb[0][idx] = v;
   }
@@ -1210,20 +1218,16 @@ __global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
         row = row < 0 ? row + D : (row >= D ? row - D : row);
         pc[w] = Po[row * PSB + lane];
       }
+      static_assert(D % SH::NW == 0, "whole row blocks per wave");
+      T acc[RW];
 #pragma unroll
-      for (int rr = 0; rr < RW; rr++) {
-        const int r = r0 + rr;
-        if (D % SH::NW == 0 || r < D) {
-          T acc0 = lane == D ? el[r * BWP + BW] : T(0), acc1 = T(0);
+      for (int rr = 0; rr < RW; rr++) acc[rr] = lane == D ? el[BW * D + r0 + rr] : T(0);
 #pragma unroll
-          for (int k = 0; k + 1 < BW; k += 2) {
-            acc0 += el[r * BWP + k] * pc[rr + k];
-            acc1 += el[r * BWP + k + 1] * pc[rr + k + 1];
-          }
-          if (BW & 1) acc0 += el[r * BWP + BW - 1] * pc[rr + BW - 1];
-          Pn[r * PSB + lane] = acc0 + acc1;
-        }
-      }
+      for (int k = 0; k < BW; k++)
+#pragma unroll
+        for (int rr = 0; rr < RW; rr++) acc[rr] += el[k * D + r0 + rr] * pc[rr + k];
+#pragma unroll
+      for (int rr = 0; rr < RW; rr++) Pn[(r0 + rr) * PSB + lane] = acc[rr];
     }
     lds_barrier();
   };
@@ -1240,8 +1244,26 @@ __global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
 
   tile_prefix<T, D, NT>(a, seq, ts, Pf, PSB, sq, sz, st);
 
-  // ---- outputs: z_{e0+m+1} = A_m z + b_m, one wave ----
-  if (wv != 0) return;  // no block barrier follows
+}
+
+// Output pass of the banded scan, a launch of its own after k_scan_band (so
+// the fold keeps few registers and four workgroups per compute unit): one
+// wave per tile walks its elements, z_{e0+m+1} = A_m z + b_m, from the
+// tile's starting vector (the previous tile's published inclusive prefix,
+// or z0).  Lane i holds row i of the band for the next PO elements in
+// registers and reads z from the extended copy zx (see above).
+template <typename T, int D, int BW, int BOFF>
+__global__ __launch_bounds__(64) void k_scan_band_out(ScanArgs a) {
+  using SH = BandScanShape<T, D, BW, BOFF>;
+  constexpr int NB = SH::NB, ZX = SH::ZX, PO = SH::PO;
+  __shared__ T zx[2][ZX];
+  const int lane = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t seq = tile % a.B, ts = tile / a.B;
+  const int64_t e0 = ts * (int64_t)a.L;
+  const int n_el = (int)((a.N - e0) < a.L ? (a.N - e0) : a.L);
+  const T* Bseq = static_cast<const T*>(a.A) + (seq * a.N + e0) * NB;
+  const T* bseq = static_cast<const T*>(a.b) + (seq * a.N + e0) * D;
   T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
   const bool act = lane < D;
   const int i = act ? lane : 0;
@@ -1250,7 +1272,12 @@ __global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
     if (i + BOFF >= D) zb[i + BOFF - D] = v;
     if (i + BOFF + D < ZX) zb[i + BOFF + D] = v;
   };
-  if (act) put(zx[0], sz[i]);
+  T zin;
+  if (ts == 0)
+    zin = a.z0 ? static_cast<const T*>(a.z0)[seq * D + i] : T(0);
+  else
+    zin = static_cast<const T*>(a.incl)[(seq * a.tiles_per_seq + ts - 1) * D + i];
+  if (act) put(zx[0], zin);
   T row[PO][BW], rbo[PO];
   auto fetch_row = [&](int m, T (&rw)[BW], T& bv) {
     const T* src = Bseq + (int64_t)m * NB + i * BW;
@@ -1260,7 +1287,8 @@ __global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
   };
 #pragma unroll
   for (int u = 0; u < PO; u++) fetch_row(min(u, n_el - 1), row[u], rbo[u]);
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): as in the fold
+  // every load complete at the loop entry (see the dense scan's fold)
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   __builtin_amdgcn_wave_barrier();
   auto out_one = [&](const int m, T (&rw)[BW], T& bv) __attribute__((always_inline)) {
     const T* zc = zx[m & 1];
@@ -1283,7 +1311,7 @@ __global__ __launch_bounds__(256) void k_scan_band(ScanArgs a) {
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
   };
-  m0 = 0;
+  int m0 = 0;  // whole groups of PO, then the rest (as in the dense scan)
   for (; m0 + PO <= n_el; m0 += PO)
 #pragma unroll
     for (int u = 0; u < PO; u++) out_one(m0 + u, row[u], rbo[u]);
@@ -1312,12 +1340,14 @@ static int scan_tile_elems(int d, int dtype, int tile) {
 }
 
 // Dense default tile length: enough tiles for one per compute unit, so the
-// chain of inclusive prefixes between tiles stays short.
+// chain of inclusive prefixes between tiles stays short; one tile per
+// sequence (no fold, see k_scan_dense) once the sequences alone fill half of
+// the compute units.
 static int dense_tile_len(int64_t B, int64_t N) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int64_t per_seq_tiles = (cus + B - 1) / B;
+  const int64_t per_seq_tiles = 2 * B >= cus ? 1 : (cus + B - 1) / B;
   int64_t L = (N + per_seq_tiles - 1) / per_seq_tiles;
   if (L < 1) L = 1;
   if (L > (1 << 20)) L = 1 << 20;
@@ -1425,12 +1455,16 @@ static bool scan_band_shape(int d, int bw, int boff) {
   return d == 40 && bw == 13 && (boff == 4 || boff == 8);
 }
 
-// Band default tile length: about four tiles per compute unit, so the output
-// pass of one tile (a single wave) overlaps the folds of the others.
+// Band default tile length.  With at least half as many sequences as compute
+// units the sequences alone fill the device: one tile per sequence, whose
+// starting vector is known, so no fold at all (the output pass is the plain
+// recursion, BW multiply-adds per entry instead of the fold's D*BW).
+// Otherwise about four tiles per compute unit.
 static int band_tile_len(int64_t B, int64_t N) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (2 * B >= cus) return (int)(N < 1 ? 1 : (N > (1 << 30) ? (1 << 30) : N));
   const int64_t per_seq_tiles = (4 * (int64_t)cus + B - 1) / B;
   int64_t L = (N + per_seq_tiles - 1) / per_seq_tiles;
   if (L < 16) L = 16;
@@ -1449,7 +1483,12 @@ size_t scan_band_ws_bytes(int d, int bw, int boff, int64_t B, int64_t N, int til
 
 template <typename T, int BOFF>
 static int launch_band(const ScanArgs& sa, int64_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_scan_band<T, 40, 13, BOFF>), dim3((unsigned)grid), dim3(256), 0, s, sa);
+  // one tile per sequence: every tile starts from z0, no aggregates needed
+  if (sa.tiles_per_seq > 1) {
+    hipLaunchKernelGGL((k_scan_band<T, 40, 13, BOFF>), dim3((unsigned)grid), dim3(256), 0, s, sa);
+    if (hipGetLastError() != hipSuccess) return ST_DEVICE;
+  }
+  hipLaunchKernelGGL((k_scan_band_out<T, 40, 13, BOFF>), dim3((unsigned)grid), dim3(64), 0, s, sa);
   return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
 }
 

@@ -69,6 +69,12 @@ def test_dense_tile_sizes(pint, orc):
         _check(pint, orc, 40, 70, 1, "f64", True, seed=7, tile=tile)
 
 
+@pytest.mark.parametrize("d", [16, 40, 128])
+def test_dense_one_tile_per_sequence(pint, orc, d):
+    """tile = N: every tile starts from z0 and the fold is skipped."""
+    _check(pint, orc, d, 150, 3, "f64", True, seed=90 + d, tile=150)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 8])
 def test_many_tiles_mixed(pint, orc, d, dtype):
@@ -134,6 +140,12 @@ def test_band_several_tiles_ragged(pint, orc, boff, dtype):
 def test_band_lengths_and_tiles(pint, orc, N, tile):
     print(f"[scan-band] N={N} tile={tile}", flush=True)
     _check_band(pint, orc, N, 2, 4, "f64", N % 2 == 0, seed=70, tile=tile)
+
+
+def test_band_one_tile_per_sequence(pint, orc):
+    """tile = N: the output pass alone, from z0 (no fold launch)."""
+    _check_band(pint, orc, 600, 3, 4, "f64", True, seed=85, tile=600)
+    _check_band(pint, orc, 600, 2, 8, "f32", False, seed=86, tile=600)
 
 
 def test_band_many_sequences(pint, orc):
