@@ -84,10 +84,22 @@ struct DenseShape {
   static_assert(D * QC <= NT, "row split");
 };
 
+// Element pass shape: steps per pass and Jacobian threads per step.  A
+// banded system builds one band column per thread (S::jac_band_column), so
+// NT / D steps fit in a pass; otherwise S::SPP steps of S::JT threads.
+template <class S, bool B = S::BANDED>
+struct ElemShape {
+  static constexpr int JT = S::JT, SPP = S::SPP;
+};
+template <class S>
+struct ElemShape<S, true> {
+  static constexpr int JT = S::D, SPP = S::NT / S::D;
+};
+
 // Shared-memory state of a dense solver workgroup.
 template <typename T, class S>
 struct DenseSmem {
-  typename S::Stage stage[S::SPP];
+  typename S::Stage stage[ElemShape<S>::SPP];
   T P[S::NP], x0[S::D], z[2][S::D];
   double red[S::NT / PINT_WAVE];
   int64_t redi[S::NT / PINT_WAVE];
@@ -138,7 +150,8 @@ __device__ __forceinline__ double dn_resid_max(DenseSmem<T, S>& sm, T dt, const 
 template <typename T, class S>
 __device__ __forceinline__ void dn_elements(DenseSmem<T, S>& sm, T dt, const T* X, int64_t lo, int64_t len,
                             int64_t m_first, int64_t m_stride, T* AT, T* bb, double* hn = nullptr) {
-  constexpr int D = S::D, NT = S::NT, NW = NT / PINT_WAVE, SPP = S::SPP, JT = S::JT;
+  constexpr int D = S::D, NT = S::NT, NW = NT / PINT_WAVE;
+  constexpr int SPP = ElemShape<S>::SPP, JT = ElemShape<S>::JT;
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
   for (int64_t g0 = m_first; g0 < len; g0 += m_stride * SPP) {
     for (int sl = wv; sl < SPP; sl += NW) {
@@ -169,10 +182,21 @@ __device__ __forceinline__ void dn_elements(DenseSmem<T, S>& sm, T dt, const T* 
       const int sl = t / JT, sub = t % JT;
       const int64_t m = g0 + sl * m_stride;
       if (m < len) {
-        if constexpr (S::BANDED)
-          S::jac_band_thread(&sm.stage[sl], sm.P, sub, dt, AT + m * S::BW * D);
-        else
+        if constexpr (S::BANDED) {
+          // column j = sub of J: rows j - BOFFT + r, stored diagonal-major
+          // at band[(BW - 1 - r) * D + row] (diagonal k = j - row + BOFF)
+          T col[S::BW];
+          S::jac_band_column(&sm.stage[sl], sub, dt, col);
+          T* band = AT + m * S::BW * D;
+#pragma unroll
+          for (int r = 0; r < S::BW; r++) {
+            int row = sub - S::BOFFT + r;
+            row = row < 0 ? row + D : (row >= D ? row - D : row);
+            band[(S::BW - 1 - r) * D + row] = col[r];
+          }
+        } else {
           S::jac_thread(&sm.stage[sl], sm.P, sub, dt, AT + m * D * D, 1, D);
+        }
       }
     }
     __syncthreads();
