@@ -150,30 +150,63 @@ __device__ __forceinline__ void aff_after(Aff<T, D>& l, const Aff<T, D>& e) {
   l = r;
 }
 
+// DPP row operations of a VALU move (gfx9): the value of another lane of
+// the same wave without an LDS round trip.  Lanes whose source is out of
+// range, or whose row is masked off, get `old`.
+constexpr int DPP_ROW_SHR = 0x110;    // + n: lane i <- lane i - n within its row of 16
+constexpr int DPP_ROW_BCAST15 = 0x142;  // rows 1, 3 (mask 0xa) <- lane 15 of the row below
+constexpr int DPP_ROW_BCAST31 = 0x143;  // rows 2, 3 (mask 0xc) <- lane 31
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_row(double old, double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_row(float old, float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+// One level of the wave scan: e <- e o (the map CTRL brings from an earlier
+// lane), on the lanes that have one.
+template <typename T, int D, int CTRL, int ROW_MASK>
+__device__ __forceinline__ void wave_scan_level(Aff<T, D>& e, bool has) {
+  Aff<T, D> o;
+#pragma unroll
+  for (int i = 0; i < D * D; i++) o.A[i] = dpp_row<CTRL, ROW_MASK>(T(0), e.A[i]);
+#pragma unroll
+  for (int i = 0; i < D; i++) o.b[i] = dpp_row<CTRL, ROW_MASK>(T(0), e.b[i]);
+  if (has) aff_after(e, o);
+}
+
+// Inclusive scan of one element per lane across the wave: e becomes the
+// composition of lanes 0..lane, earliest applied first.  Kogge-Stone within
+// rows of 16 lanes (shifts 1, 2, 4, 8), then the rows joined by broadcasts
+// of lane 15 (to rows 1, 3) and lane 31 (to rows 2, 3); all DPP moves.
 template <typename T, int D>
-__device__ __forceinline__ void aff_shfl_up(Aff<T, D>& out, const Aff<T, D>& in, int delta) {
-#pragma unroll
-  for (int i = 0; i < D * D; i++) out.A[i] = __shfl_up(in.A[i], delta, PINT_WAVE);
-#pragma unroll
-  for (int i = 0; i < D; i++) out.b[i] = __shfl_up(in.b[i], delta, PINT_WAVE);
+__device__ __forceinline__ void wave_scan_aff(Aff<T, D>& e) {
+  const int lane = threadIdx.x % PINT_WAVE, r = lane & 15;
+  wave_scan_level<T, D, DPP_ROW_SHR + 1, 0xf>(e, r >= 1);
+  wave_scan_level<T, D, DPP_ROW_SHR + 2, 0xf>(e, r >= 2);
+  wave_scan_level<T, D, DPP_ROW_SHR + 4, 0xf>(e, r >= 4);
+  wave_scan_level<T, D, DPP_ROW_SHR + 8, 0xf>(e, r >= 8);
+  wave_scan_level<T, D, DPP_ROW_BCAST15, 0xa>(e, (lane & 16) != 0);
+  wave_scan_level<T, D, DPP_ROW_BCAST31, 0xc>(e, lane >= 32);
 }
 
 // Inclusive scan of one element per thread across a block of NT threads
 // (NT/64 waves): on return e is the composition of the elements of threads
 // 0..threadIdx.x, earliest applied first.  `lds` holds NT/64 elements.
-// Kogge-Stone inside each wave via shuffles, then wave aggregates through
-// LDS.  Contains two __syncthreads.
-template <typename T, int D, int NT>
+// The wave scan in DPP moves, then wave aggregates through LDS.  Contains
+// two workgroup barriers: full ones, or (LDS_ONLY) ones that order LDS only
+// and leave this thread's global loads in flight.
+template <typename T, int D, int NT, bool LDS_ONLY = false>
 __device__ __forceinline__ void block_scan_aff(Aff<T, D>& e, Aff<T, D>* lds) {
   const int lane = threadIdx.x % PINT_WAVE, w = threadIdx.x / PINT_WAVE;
-#pragma unroll
-  for (int off = 1; off < PINT_WAVE; off <<= 1) {
-    Aff<T, D> prev;
-    aff_shfl_up(prev, e, off);
-    if (lane >= off) aff_after(e, prev);
-  }
+  wave_scan_aff<T, D>(e);
   if (lane == PINT_WAVE - 1) lds[w] = e;
-  __syncthreads();
+  if constexpr (LDS_ONLY) lds_barrier(); else __syncthreads();
   if (w > 0) {
     Aff<T, D> c = lds[0];
     for (int i = 1; i < w; i++) {
@@ -183,7 +216,7 @@ __device__ __forceinline__ void block_scan_aff(Aff<T, D>& e, Aff<T, D>* lds) {
     }
     aff_after(e, c);
   }
-  __syncthreads();
+  if constexpr (LDS_ONLY) lds_barrier(); else __syncthreads();
 }
 
 // ---------------------------------------------------------------- atomics --

@@ -187,11 +187,53 @@ __device__ __forceinline__ void stage_out(T* __restrict__ g, const T* lds, int n
   }
 }
 
+// A run of RUN scalars per thread in registers, in the striped order of
+// stage_in (vector j of thread t covers scalars (j*NT + t)*V ..): fetched
+// from global memory ahead of its use, then stashed into the padded LDS
+// layout, so a chunk's loads fly while the previous chunk is composed.
+template <typename T, int RUN, int V>
+struct RunRegs {
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  vec_t r[RUN / V];
+};
+
+template <typename T, int RUN, int V, int NT>
+__device__ __forceinline__ void fetch_run(const T* __restrict__ g, int n, int tid, RunRegs<T, RUN, V>& R) {
+  using vec_t = typename RunRegs<T, RUN, V>::vec_t;
+  constexpr int NV = RUN / V;
+  if (n == NT * RUN && (reinterpret_cast<uintptr_t>(g) % (V * sizeof(T))) == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; j++) R.r[j] = reinterpret_cast<const vec_t*>(g)[j * NT + tid];
+  } else {
+#pragma unroll
+    for (int j = 0; j < NV; j++)
+#pragma unroll
+      for (int c = 0; c < V; c++) {
+        const int q = (j * NT + tid) * V + c;
+        R.r[j][c] = q < n ? g[q] : T(0);
+      }
+  }
+}
+
+template <typename T, int RUN, int V, int NT>
+__device__ __forceinline__ void stash_run(T* lds, int n, int tid, const RunRegs<T, RUN, V>& R) {
+  constexpr int NV = RUN / V;
+#pragma unroll
+  for (int j = 0; j < NV; j++)
+#pragma unroll
+    for (int c = 0; c < V; c++) {
+      const int q = (j * NT + tid) * V + c;
+      if (q < n) lds[q + q / RUN] = R.r[j][c];
+    }
+}
+
 // A tile is C chunks of NT*S elements.  Pass 1 stages the chunks in turn
 // and composes their aggregates into the tile's; after the lookback, pass 2
 // stages them again (the second read mostly hits the last-level cache) and
 // writes the outputs with z carried from chunk to chunk.  One lookback per
-// C chunks: the lookback's latency, not bandwidth, bounds the scan.
+// C chunks.  A chunk's loads go to registers one chunk ahead (the first of
+// pass 2 during the lookback), and the barriers between order LDS only, so
+// the loads stay in flight while the previous chunk is composed.
 template <typename T, int D>
 __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs a) {
   using SH = SmallShape<D, T>;
@@ -219,15 +261,24 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
   const T* myA = sA + tid * PA;
   const T* myb = sb + tid * PB;
 
-  // chunk c into LDS; each thread folds its S elements; block scan:
-  // agg = composition of threads 0..tid of the chunk
+  RunRegs<T, RA, SH::VA> rA;
+  RunRegs<T, RB, SH::VB> rB;
+  auto chunk_len = [&](int c) { return (n_el - c * CH) < CH ? (n_el - c * CH) : CH; };
+  auto fetch = [&](int c) {
+    const int c0 = c * CH, n = chunk_len(c);
+    fetch_run<T, RA, SH::VA, NT>(Ag + (int64_t)c0 * D * D, n * D * D, tid, rA);
+    fetch_run<T, RB, SH::VB, NT>(bg + (int64_t)c0 * D, n * D, tid, rB);
+  };
+  // chunk c (its registers) into LDS, the next chunk's loads issued; each
+  // thread folds its S elements; block scan: agg = composition of threads
+  // 0..tid of the chunk
   auto chunk_scan = [&](int c, bool load, Aff<T, D>& agg, int& cn) {
-    const int c0 = c * CH;
-    cn = (n_el - c0) < CH ? (n_el - c0) : CH;
+    cn = chunk_len(c);
     if (load) {
-      stage_in<T, RA, SH::VA, NT>(Ag + (int64_t)c0 * D * D, sA, cn * D * D, tid);
-      stage_in<T, RB, SH::VB, NT>(bg + (int64_t)c0 * D, sb, cn * D, tid);
-      __syncthreads();
+      stash_run<T, RA, SH::VA, NT>(sA, cn * D * D, tid, rA);
+      stash_run<T, RB, SH::VB, NT>(sb, cn * D, tid, rB);
+      lds_barrier();
+      if (c + 1 < nch) fetch(c + 1);
     }
     aff_identity(agg);
 #pragma unroll
@@ -242,12 +293,13 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
         agg = e;
       }
     }
-    block_scan_aff<T, D, NT>(agg, s_aff);
+    block_scan_aff<T, D, NT, true>(agg, s_aff);
   };
 
   // pass 1: the tile's aggregate
   Aff<T, D> agg;
   int cn = 0;
+  fetch(0);
   for (int c = 0; c < nch; c++) {
     chunk_scan(c, true, agg, cn);
     if (tid == NT - 1) {
@@ -255,8 +307,11 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
       aff_after(t, s_tagg);  // this chunk after the earlier ones
       s_tagg = t;
     }
-    __syncthreads();  // s_tagg updated; the chunk's LDS may be rewritten
+    lds_barrier();  // s_tagg updated; the chunk's LDS may be rewritten
   }
+  // pass 2's first chunk loads during the lookback (wave 0's share after
+  // it: its flag stores wait for all of its outstanding memory operations)
+  if (nch > 1 && wv != 0) fetch(0);
 
   // lookback by wave 0: z at the start of this tile
   if (wv == 0) {
@@ -339,8 +394,9 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
       }
       publish_flag(flags + ts, FLAG_INCL);
     }
+    if (nch > 1) fetch(0);
   }
-  __syncthreads();
+  lds_barrier();  // s_zin written (the prefetched loads stay in flight)
 
   // pass 2: outputs chunk by chunk (a one-chunk tile is still in LDS)
   T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
@@ -360,7 +416,7 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
     if (lane == PINT_WAVE - 1)
 #pragma unroll
       for (int i = 0; i < D; i++) s_wz[wv][i] = zend[i];
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < D; i++) {
       const T up = __shfl_up(zend[i], 1, PINT_WAVE);
@@ -385,7 +441,7 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
         }
       }
     }
-    __syncthreads();  // every thread has read s_zin, s_wz and its b run
+    lds_barrier();  // every thread has read s_zin, s_wz and its b run
     if (tid == NT - 1)  // the next chunk starts where this one ends
 #pragma unroll
       for (int i = 0; i < D; i++) s_zin[i] = zend[i];
@@ -395,9 +451,9 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
 #pragma unroll
         for (int i = 0; i < D; i++) sb[tid * PB + s * D + i] = out[s][i];
     }
-    __syncthreads();
+    lds_barrier();
     stage_out<T, RB, SH::VB, NT>(zg + (int64_t)c * CH * D, sb, cn * D, tid);
-    __syncthreads();  // the staging area is reloaded by the next chunk
+    lds_barrier();  // the staging area is reloaded by the next chunk
   }
 }
 
