@@ -230,10 +230,13 @@ __device__ __forceinline__ void stash_run(T* lds, int n, int tid, const RunRegs<
 // A tile is C chunks of NT*S elements.  Pass 1 stages the chunks in turn
 // and composes their aggregates into the tile's; after the lookback, pass 2
 // stages them again (the second read mostly hits the last-level cache) and
-// writes the outputs with z carried from chunk to chunk.  One lookback per
-// C chunks.  A chunk's loads go to registers one chunk ahead (the first of
-// pass 2 during the lookback), and the barriers between order LDS only, so
-// the loads stay in flight while the previous chunk is composed.
+// writes the outputs.  One lookback per C chunks.  Pass 1 keeps each chunk's
+// aggregate, so after the lookback the z at every chunk start is known and
+// pass 2 walks the chunks backwards: the last one is still in LDS and the
+// others come back most recent first, while they are likeliest to be cached.
+// A chunk's loads go to registers one chunk ahead (the first of pass 2
+// during the lookback), and the barriers between order LDS only, so the
+// loads stay in flight while the previous chunk is composed.
 template <typename T, int D>
 __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs a) {
   using SH = SmallShape<D, T>;
@@ -243,7 +246,9 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
   __shared__ T sb[NT * PB];
   __shared__ Aff<T, D> s_aff[NW];
   __shared__ Aff<T, D> s_tagg;
-  __shared__ T s_zin[D], s_wz[NW][D];
+  __shared__ Aff<T, D> s_cagg[SH::C];  // each chunk's aggregate (pass 1)
+  __shared__ T s_zc[SH::C][D];         // z at each chunk start (after the lookback)
+  __shared__ T s_wz[NW][D];
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
   if (tid == 0) {
@@ -269,17 +274,15 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
     fetch_run<T, RA, SH::VA, NT>(Ag + (int64_t)c0 * D * D, n * D * D, tid, rA);
     fetch_run<T, RB, SH::VB, NT>(bg + (int64_t)c0 * D, n * D, tid, rB);
   };
-  // chunk c (its registers) into LDS, the next chunk's loads issued; each
-  // thread folds its S elements; block scan: agg = composition of threads
-  // 0..tid of the chunk
-  auto chunk_scan = [&](int c, bool load, Aff<T, D>& agg, int& cn) {
+  // chunk c (its registers) into LDS, the loads of chunk `next` (if >= 0)
+  // issued; each thread folds its S elements; block scan: agg = composition
+  // of threads 0..tid of the chunk
+  auto chunk_scan = [&](int c, int next, Aff<T, D>& agg, int& cn) {
     cn = chunk_len(c);
-    if (load) {
-      stash_run<T, RA, SH::VA, NT>(sA, cn * D * D, tid, rA);
-      stash_run<T, RB, SH::VB, NT>(sb, cn * D, tid, rB);
-      lds_barrier();
-      if (c + 1 < nch) fetch(c + 1);
-    }
+    stash_run<T, RA, SH::VA, NT>(sA, cn * D * D, tid, rA);
+    stash_run<T, RB, SH::VB, NT>(sb, cn * D, tid, rB);
+    lds_barrier();
+    if (next >= 0) fetch(next);
     aff_identity(agg);
 #pragma unroll
     for (int s = 0; s < S; s++) {
@@ -301,18 +304,20 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
   int cn = 0;
   fetch(0);
   for (int c = 0; c < nch; c++) {
-    chunk_scan(c, true, agg, cn);
+    chunk_scan(c, c + 1 < nch ? c + 1 : -1, agg, cn);
     if (tid == NT - 1) {
+      s_cagg[c] = agg;
       Aff<T, D> t = agg;
       aff_after(t, s_tagg);  // this chunk after the earlier ones
       s_tagg = t;
     }
-    lds_barrier();  // s_tagg updated; the chunk's LDS may be rewritten
+    if (c + 1 < nch) lds_barrier();  // the chunk's LDS may be rewritten
   }
-  // pass 2's first chunk loads during the lookback (wave 0's share after
-  // it: its flag stores wait for all of its outstanding memory operations)
-  if (nch > 1 && wv != 0) fetch(0);
-
+  // pass 2's first reload (chunk nch-2) during the lookback (wave 0's share
+  // after it: its flag stores wait for all of its outstanding memory
+  // operations); the last chunk is still in LDS and `agg` is its scan
+  if (nch > 1 && wv != 0) fetch(nch - 2);
+  lds_barrier();  // s_tagg, s_cagg written
   // lookback by wave 0: z at the start of this tile
   if (wv == 0) {
     const int64_t base = seq * a.tiles_per_seq;
@@ -382,8 +387,27 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
       }
     }
     if (lane == 0) {
+      // z at each chunk start
 #pragma unroll
-      for (int i = 0; i < D; i++) s_zin[i] = z[i];
+      for (int i = 0; i < D; i++) s_zc[0][i] = z[i];
+      T zc[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) zc[i] = z[i];
+      for (int c = 1; c < nch; c++) {
+        T t[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          T acc = s_cagg[c - 1].b[i];
+#pragma unroll
+          for (int q = 0; q < D; q++) acc += s_cagg[c - 1].A[i * D + q] * zc[q];
+          t[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          zc[i] = t[i];
+          s_zc[c][i] = t[i];
+        }
+      }
       // this tile's inclusive prefix: its aggregate applied to z_in
 #pragma unroll
       for (int i = 0; i < D; i++) {
@@ -394,18 +418,18 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
       }
       publish_flag(flags + ts, FLAG_INCL);
     }
-    if (nch > 1) fetch(0);
+    if (nch > 1) fetch(nch - 2);
   }
-  lds_barrier();  // s_zin written (the prefetched loads stay in flight)
+  lds_barrier();  // s_zc written (the prefetched loads stay in flight)
 
-  // pass 2: outputs chunk by chunk (a one-chunk tile is still in LDS)
+  // pass 2: outputs chunk by chunk, last chunk first (it is still in LDS)
   T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
-  for (int c = 0; c < nch; c++) {
-    if (nch > 1) chunk_scan(c, true, agg, cn);
+  for (int c = nch - 1; c >= 0; c--) {
+    if (c < nch - 1) chunk_scan(c, c > 0 ? c - 1 : -1, agg, cn);
     // z at the end of each thread's run, then at its start (previous thread)
     T zin[D], zend[D], z[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) zin[i] = s_zin[i];
+    for (int i = 0; i < D; i++) zin[i] = s_zc[c][i];
 #pragma unroll
     for (int i = 0; i < D; i++) {
       T acc = agg.b[i];
@@ -441,10 +465,7 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
         }
       }
     }
-    lds_barrier();  // every thread has read s_zin, s_wz and its b run
-    if (tid == NT - 1)  // the next chunk starts where this one ends
-#pragma unroll
-      for (int i = 0; i < D; i++) s_zin[i] = zend[i];
+    lds_barrier();  // every thread has read s_wz and its b run
 #pragma unroll
     for (int s = 0; s < S; s++) {
       if (tid * S + s < cn)
