@@ -117,7 +117,7 @@ struct SmallShape {
   static constexpr int S0 = 49152 / (E * (int)sizeof(T) * NT);
   static constexpr int S = S0 < 1 ? 1 : (S0 > 16 ? 16 : S0);
   static constexpr int CH = NT * S;   // elements per chunk (one LDS staging)
-  static constexpr int C = 8;         // chunks per tile (one lookback per tile)
+  static constexpr int C = D == 1 ? 12 : 8;  // chunks per tile (one lookback per tile)
   static constexpr int TILE = CH * C;
   static constexpr int RA = S * D * D, RB = S * D;
   static constexpr int VA = vec_width<T>(RA), VB = vec_width<T>(RB);
