@@ -181,14 +181,22 @@ def leg_vdp_batch(P, torch, dev, stream, reps=3, window=256):
     return out
 
 
-def leg_adjoint(P, torch, dev, stream, B=256, T=16384, window=32, seg=2048, reps=2):
+def leg_adjoint(P, torch, dev, stream, B=256, T=16384, window=0, seg=2048, reps=2):
     """Adjoint on Lorenz-96 (d=40, T=16384, 256 instances): forward windowed
-    Newton solve, loss over 64 observations, gradients w.r.t. x0 and F by the
-    reverse scan.  grads/s = instances / backward time."""
+    Newton solve (window 0: picked by the autotuner among 16, 24, 32, 48), loss
+    over 64 observations, gradients w.r.t. x0 and F by the reverse scan.
+    grads/s = instances / backward time."""
     import workloads as W
-    w = W.adjoint_l96(B=B, T=T, window=window)
+    from paper_2511_01465_amd import autotune
+    w = W.adjoint_l96(B=B, T=T, window=window or 32)
     x0 = torch.tensor(w.x0, device=dev)
     prm = torch.tensor(w.params, device=dev)
+    tuning = None
+    if not window:
+        cfg = autotune.tune_window(P.LORENZ96, x0, prm, w.dt, T, tol=1e-10, windows=(16, 24, 32, 48),
+                                   reps=1, cache=None, stream=stream)
+        window = cfg["window"]
+        tuning = {str(t["window"]): round(t["ms"], 2) for t in cfg["trials"]}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     traj, iters, resid, status = P.solve(P.LORENZ96, x0, prm, w.dt, T, tol=1e-10, window=window)
@@ -205,7 +213,8 @@ def leg_adjoint(P, torch, dev, stream, B=256, T=16384, window=32, seg=2048, reps
         res["g"] = P.adjoint(P.LORENZ96, x0, prm, w.dt, traj, g, seg=seg)
 
     ms = _time(back, reps, stream)
-    return {"instances": B, "T": T, "forward_ms": fwd_ms, "forward_all_ok": bool((status == 0).all()),
+    return {"instances": B, "T": T, "forward_window": window, "forward_window_tuning": tuning,
+            "forward_ms": fwd_ms, "forward_all_ok": bool((status == 0).all()),
             "backward_ms": ms, "grads_per_s": B / (ms / 1e3), "segment": seg,
             "fwd_plus_bwd_grads_per_s": B / ((ms + fwd_ms) / 1e3)}
 
