@@ -52,7 +52,7 @@ def test_small_d_several_tiles_ragged(pint, orc, d, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("d", [16, 40, 128])
+@pytest.mark.parametrize("d", [16, 32, 40, 64, 128])
 def test_dense_d_several_tiles_ragged(pint, orc, d, dtype):
     N = 16 * 5 + 3
     print(f"[scan] d={d} {dtype} N={N}", flush=True)
