@@ -22,8 +22,10 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 # System identifiers (same numbering as the public C interface).
-LINEAR, LOGISTIC, VDP, CARTPOLE, LORENZ63, LORENZ96, KURAMOTO = range(7)
+LINEAR, LOGISTIC, VDP, CARTPOLE, LORENZ63, LORENZ96, KURAMOTO, ROBERTSON = range(8)
 OK, NOT_CONVERGED, NONFINITE = 0, 4, 5
+# One-step rules: explicit RK4, backward Euler, trapezoidal (Sec. 3.4).
+RK4, BEULER, TRAP = range(3)
 
 _lib = None
 
@@ -62,6 +64,10 @@ def _load():
         "orc_affine_seq": (None, [i, i64, dp, dp, dp, dp]),
         "orc_combine": (None, [i, dp, dp, dp, dp, dp, dp]),
         "orc_newton": (i, [i, i, dp, d, i64, dp, dp, d, i64, i64, d, dp, i64p, dp]),
+        "orc_residual_implicit": (None, [i, i, i, dp, d, i64, dp, dp, i, dp]),
+        "orc_integrate_implicit": (i, [i, i, i, dp, d, i64, dp, dp]),
+        "orc_newton_implicit": (i, [i, i, i, dp, d, i64, dp, dp, d, i64, i64, d, dp,
+                                    i64p, dp]),
         "orc_adjoint": (i, [i, i, dp, d, i64, dp, dp, dp, dp, dp]),
         "orc_tangent": (i, [i, i, dp, d, i64, dp, dp, dp, dp, dp]),
     }
@@ -203,6 +209,55 @@ def newton(sys, params, dt, T, x0, guess=None, tol=1e-10, max_iter=None,
     st = _load().orc_newton(sys, d, _p(_f64(params)), dt, T, _p(x0), _p(traj),
                             tol, int(max_iter), int(window), guard, _p(hist),
                             C.byref(iters), C.byref(fres))
+    k = iters.value
+    return dict(traj=traj, status=st, iters=k, final_resid=fres.value,
+                hist=hist[: k + 1].copy())
+
+
+def integrate_implicit(method, sys, params, dt, T, x0):
+    """O1 for an implicit rule (BEULER or TRAP): each step solved by Newton's
+    method to rounding; [T, d]."""
+    x0 = _f64(x0)
+    d = x0.size
+    traj = np.empty((int(T), d))
+    rc = _load().orc_integrate_implicit(method, sys, d, _p(_f64(params)), dt, int(T),
+                                        _p(x0), _p(traj))
+    if rc != 0:
+        raise ArithmeticError("a step of the implicit integration did not converge")
+    return traj
+
+
+def residual_implicit(method, sys, params, dt, x0, traj, scaled=False):
+    """h_n = x_n - x_{n-1} - g_{n-1}(x_{n-1}, x_n), n = 1..T, as [T, d]; with
+    scaled, (I - dg_{n-1}/dx_n)^{-1} h_n."""
+    x0 = _f64(x0)
+    d = x0.size
+    traj = _f64(traj).reshape(-1, d)
+    h = np.empty_like(traj)
+    _load().orc_residual_implicit(method, sys, d, _p(_f64(params)), dt, traj.shape[0],
+                                  _p(x0), _p(traj), int(bool(scaled)), _p(h))
+    return h
+
+
+def newton_implicit(method, sys, params, dt, T, x0, guess=None, tol=1e-10,
+                    max_iter=None, window=0, guard=1e6):
+    """O2 for an implicit rule.  Same arguments and result as newton(); the
+    residual in hist / final_resid is the scaled one."""
+    x0 = _f64(x0)
+    d = x0.size
+    T = int(T)
+    if guess is None:
+        traj = np.tile(x0, (T, 1)) if T > 0 else np.empty((0, d))
+    else:
+        traj = _f64(guess).reshape(T, d).copy()
+    if max_iter is None:
+        max_iter = T + 1
+    hist = np.full(int(max_iter) + 1, np.nan)
+    iters = C.c_int64(0)
+    fres = C.c_double(0.0)
+    st = _load().orc_newton_implicit(method, sys, d, _p(_f64(params)), dt, T, _p(x0),
+                                     _p(traj), tol, int(max_iter), int(window), guard,
+                                     _p(hist), C.byref(iters), C.byref(fres))
     k = iters.value
     return dict(traj=traj, status=st, iters=k, final_resid=fres.value,
                 hist=hist[: k + 1].copy())

@@ -49,8 +49,14 @@ enum {
   ORC_CARTPOLE = 3,
   ORC_LORENZ63 = 4,
   ORC_LORENZ96 = 5,
-  ORC_KURAMOTO = 6
+  ORC_KURAMOTO = 6,
+  ORC_ROBERTSON = 7
 };
+
+/* One-step rules: the explicit RK4 step, and the implicit rules of
+ * eq. (implicit-ode) with g_n = dt f(x_{n+1}) (backward Euler,
+ * eq. implicit-euler) or g_n = dt/2 (f(x_n) + f(x_{n+1})) (trapezoidal). */
+enum { ORC_RK4 = 0, ORC_BEULER = 1, ORC_TRAP = 2 };
 
 /* Status codes returned by orc_newton (same numbering as the C interface). */
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 4, ORC_NONFINITE = 5 };
@@ -66,6 +72,7 @@ int orc_n_params(int sys, int d) {
     case ORC_LORENZ63: return d == 3 ? 3 : -1;         /* sigma, rho, beta*/
     case ORC_LORENZ96: return d >= 4 ? 1 : -1;         /* F               */
     case ORC_KURAMOTO: return d >= 1 ? d + 1 : -1;     /* K, omega_1..d   */
+    case ORC_ROBERTSON: return d == 3 ? 3 : -1;        /* k1, k2, k3      */
   }
   return -1;
 }
@@ -128,6 +135,11 @@ void orc_f(int sys, int d, const double* P, const double* x, double* out) {
         for (j = 0; j < d; j++) acc += sin(x[j] - x[i]);
         out[i] = P[1 + i] + P[0] * acc;
       }
+      break;
+    case ORC_ROBERTSON: /* eq. (robertson), P = (k1, k2, k3) */
+      out[0] = -P[0] * x[0] + P[2] * x[1] * x[2];
+      out[1] = P[0] * x[0] - P[1] * x[1] * x[1] - P[2] * x[1] * x[2];
+      out[2] = P[1] * x[1] * x[1];
       break;
   }
 }
@@ -193,6 +205,11 @@ void orc_jf(int sys, int d, const double* P, const double* x, double* J) {
         J[i * d + i] = diag;
       }
       break;
+    case ORC_ROBERTSON:
+      J[0] = -P[0]; J[1] = P[2] * x[2]; J[2] = P[2] * x[1];
+      J[3] = P[0]; J[4] = -2.0 * P[1] * x[1] - P[2] * x[2]; J[5] = -P[2] * x[1];
+      J[6] = 0.0; J[7] = 2.0 * P[1] * x[1]; J[8] = 0.0;
+      break;
   }
 }
 
@@ -230,6 +247,11 @@ int orc_ftheta(int sys, int d, const double* P, const double* x, double* G) {
         G[i * np + 0] = acc;
         G[i * np + 1 + i] = 1.0;
       }
+      return 0;
+    case ORC_ROBERTSON:
+      G[0 * 3 + 0] = -x[0]; G[0 * 3 + 2] = x[1] * x[2];
+      G[1 * 3 + 0] = x[0]; G[1 * 3 + 1] = -x[1] * x[1]; G[1 * 3 + 2] = -x[1] * x[2];
+      G[2 * 3 + 1] = x[1] * x[1];
       return 0;
   }
   return -1;
@@ -585,6 +607,272 @@ int orc_newton(int sys, int d, const double* P, double dt, int64_t T,
   free(dx);
   free(J);
   free(phi);
+  return status;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Implicit one-step rules (Sec. 3.4)                                      */
+/* ---------------------------------------------------------------------- */
+
+/* g = g_{n-1}(x_{n-1}, x_n) of eq. (implicit-ode) and its partial
+ * derivatives Gp = dg/dx_{n-1}, Gc = dg/dx_n (d x d, row-major):
+ *   backward Euler: g = dt f(x_n),                Gp = 0,            Gc = dt Jf(x_n);
+ *   trapezoidal:    g = dt/2 (f(x_{n-1}) + f(x_n)), Gp = dt/2 Jf(x_{n-1}), Gc = dt/2 Jf(x_n). */
+static void implicit_g(int method, int sys, int d, const double* P, double dt,
+                       const double* xp, const double* xc, double* g, double* Gp,
+                       double* Gc) {
+  size_t dd = (size_t)d * (size_t)d;
+  double* w = (double*)malloc(sizeof(double) * (size_t)d);
+  int i;
+  if (method == ORC_BEULER) {
+    orc_f(sys, d, P, xc, g);
+    for (i = 0; i < d; i++) g[i] *= dt;
+    if (Gp) memset(Gp, 0, sizeof(double) * dd);
+    if (Gc) {
+      orc_jf(sys, d, P, xc, Gc);
+      for (size_t q = 0; q < dd; q++) Gc[q] *= dt;
+    }
+  } else { /* ORC_TRAP */
+    orc_f(sys, d, P, xp, g);
+    orc_f(sys, d, P, xc, w);
+    for (i = 0; i < d; i++) g[i] = 0.5 * dt * g[i] + 0.5 * dt * w[i];
+    if (Gp) {
+      orc_jf(sys, d, P, xp, Gp);
+      for (size_t q = 0; q < dd; q++) Gp[q] *= 0.5 * dt;
+    }
+    if (Gc) {
+      orc_jf(sys, d, P, xc, Gc);
+      for (size_t q = 0; q < dd; q++) Gc[q] *= 0.5 * dt;
+    }
+  }
+  free(w);
+}
+
+/* Solve M X = B for d x d M and B with nrhs columns (row-major, B
+ * overwritten by X), Gaussian elimination with partial pivoting on a copy
+ * of M.  Returns -1 when a pivot is exactly zero. */
+static int solve_lin(int d, const double* M, double* B, int nrhs) {
+  double* A = (double*)malloc(sizeof(double) * (size_t)d * (size_t)d);
+  memcpy(A, M, sizeof(double) * (size_t)d * (size_t)d);
+  int rc = 0;
+  for (int c = 0; c < d; c++) {
+    int piv = c;
+    for (int r = c + 1; r < d; r++)
+      if (fabs(A[r * d + c]) > fabs(A[piv * d + c])) piv = r;
+    if (A[piv * d + c] == 0.0) { rc = -1; break; }
+    if (piv != c) {
+      for (int k = 0; k < d; k++) {
+        double t = A[c * d + k]; A[c * d + k] = A[piv * d + k]; A[piv * d + k] = t;
+      }
+      for (int k = 0; k < nrhs; k++) {
+        double t = B[c * nrhs + k]; B[c * nrhs + k] = B[piv * nrhs + k]; B[piv * nrhs + k] = t;
+      }
+    }
+    for (int r = c + 1; r < d; r++) {
+      double l = A[r * d + c] / A[c * d + c];
+      for (int k = c; k < d; k++) A[r * d + k] -= l * A[c * d + k];
+      for (int k = 0; k < nrhs; k++) B[r * nrhs + k] -= l * B[c * nrhs + k];
+    }
+  }
+  if (rc == 0)
+    for (int c = d - 1; c >= 0; c--)
+      for (int k = 0; k < nrhs; k++) {
+        double acc = B[c * nrhs + k];
+        for (int q = c + 1; q < d; q++) acc -= A[c * d + q] * B[q * nrhs + k];
+        B[c * nrhs + k] = acc / A[c * d + c];
+      }
+  free(A);
+  return rc;
+}
+
+/* h_n = x_n - x_{n-1} - g_{n-1}(x_{n-1}, x_n), n = 1..T, of eq.
+ * (root-finding-problem-implicit); h[n-1] receives h_n.  With `scaled`, the
+ * quantity the paper plots for its implicit solver instead:
+ * (I - dg_{n-1}/dx_n)^{-1} h_n (a reading: its printed first values are
+ * these, not ||h||; e.g. 1/(1 + dt) for the Dahlquist problem from the
+ * zero guess, where h_1 = -x_0). */
+void orc_residual_implicit(int method, int sys, int d, const double* P, double dt,
+                           int64_t T, const double* x0, const double* traj, int scaled,
+                           double* h) {
+  size_t sd = (size_t)d;
+  double* g = (double*)malloc(sizeof(double) * sd);
+  double* Gc = (double*)malloc(sizeof(double) * sd * sd);
+  for (int64_t n = 1; n <= T; n++) {
+    const double* xp = n == 1 ? x0 : traj + (size_t)(n - 2) * sd;
+    const double* xc = traj + (size_t)(n - 1) * sd;
+    double* hn = h + (size_t)(n - 1) * sd;
+    implicit_g(method, sys, d, P, dt, xp, xc, g, NULL, Gc);
+    for (int i = 0; i < d; i++) hn[i] = xc[i] - xp[i] - g[i];
+    if (scaled) {
+      for (size_t q = 0; q < sd * sd; q++) Gc[q] = -Gc[q];
+      for (int i = 0; i < d; i++) Gc[i * d + i] += 1.0;
+      if (solve_lin(d, Gc, hn, 1) != 0)
+        for (int i = 0; i < d; i++) hn[i] = NAN;
+    }
+  }
+  free(g);
+  free(Gc);
+}
+
+/* O1 for an implicit rule: x_n solves x_n - x_{n-1} - g(x_{n-1}, x_n) = 0,
+ * step by step, by Newton's method from x_{n-1} until the correction is
+ * below 4 eps |x_n| (at most 100 corrections per step).  traj[n-1] = x_n.
+ * Returns 0, or -1 if a step did not converge. */
+int orc_integrate_implicit(int method, int sys, int d, const double* P, double dt,
+                           int64_t T, const double* x0, double* traj) {
+  size_t sd = (size_t)d;
+  double* g = (double*)malloc(sizeof(double) * sd);
+  double* M = (double*)malloc(sizeof(double) * sd * sd);
+  double* r = (double*)malloc(sizeof(double) * sd);
+  int rc = 0;
+  const double* prev = x0;
+  for (int64_t n = 1; n <= T && rc == 0; n++) {
+    double* y = traj + (size_t)(n - 1) * sd;
+    for (int i = 0; i < d; i++) y[i] = prev[i];
+    int ok = 0;
+    for (int it = 0; it < 100; it++) {
+      implicit_g(method, sys, d, P, dt, prev, y, g, NULL, M);
+      for (size_t q = 0; q < sd * sd; q++) M[q] = -M[q];
+      for (int i = 0; i < d; i++) M[i * d + i] += 1.0;
+      for (int i = 0; i < d; i++) r[i] = y[i] - prev[i] - g[i];
+      if (solve_lin(d, M, r, 1) != 0) break;
+      double dn = 0.0, yn = 0.0;
+      for (int i = 0; i < d; i++) {
+        y[i] -= r[i];
+        if (fabs(r[i]) > dn) dn = fabs(r[i]);
+        if (fabs(y[i]) > yn) yn = fabs(y[i]);
+      }
+      if (dn <= 4.0 * 2.220446049250313e-16 * yn) { ok = 1; break; }
+    }
+    if (!ok) rc = -1;
+    prev = y;
+  }
+  free(g);
+  free(M);
+  free(r);
+  return rc;
+}
+
+/*
+ * O2 for an implicit rule: Newton's method on eq. (root-finding-problem-
+ * implicit) with the step of eq. (newton-step-implicit-recursion),
+ *   dx_1 = -(I - dg_0/dx_1)^{-1} h_1,
+ *   dx_n = -(I - dg_{n-1}/dx_n)^{-1} [(-I - dg_{n-1}/dx_{n-1}) dx_{n-1} + h_n],
+ * evaluated in order.  The residual recorded in hist, tested against tol
+ * and returned in *final_resid is the scaled one of orc_residual_implicit
+ * (max over steps and components).  Plain (window <= 0) and windowed forms
+ * as in orc_newton, with p the first step whose scaled residual is >= tol.
+ * A singular (I - dg/dx_n) stops with ORC_NONFINITE.
+ */
+int orc_newton_implicit(int method, int sys, int d, const double* P, double dt,
+                        int64_t T, const double* x0, double* traj, double tol,
+                        int64_t max_iter, int64_t window, double guard, double* hist,
+                        int64_t* iters, double* final_resid) {
+  size_t sd = (size_t)d, dd = sd * sd;
+  int status = ORC_OK;
+  int64_t k = 0;
+  if (T <= 0) {
+    if (iters) *iters = 0;
+    if (final_resid) *final_resid = 0.0;
+    return ORC_OK;
+  }
+  double* h = (double*)malloc(sizeof(double) * (size_t)T * sd);
+  double* dx = (double*)malloc(sizeof(double) * (size_t)T * sd);
+  double* g = (double*)malloc(sizeof(double) * sd);
+  double* Gp = (double*)malloc(sizeof(double) * dd);
+  double* Gc = (double*)malloc(sizeof(double) * dd);
+  double* v = (double*)malloc(sizeof(double) * sd);
+  double* hs = (double*)malloc(sizeof(double) * sd);
+  int plain = (window <= 0);
+  int64_t p = 1;
+
+  /* dx over [lo, hi] from dx_{lo-1} = 0; returns -1 on a singular step */
+  #define STEP_RANGE(lo, hi)                                                     \
+    for (int64_t n = (lo); n <= (hi); n++) {                                     \
+      const double* xp = n == 1 ? x0 : traj + (size_t)(n - 2) * sd;             \
+      const double* xc = traj + (size_t)(n - 1) * sd;                            \
+      double* dn = dx + (size_t)(n - 1) * sd;                                    \
+      implicit_g(method, sys, d, P, dt, xp, xc, g, Gp, Gc);                      \
+      for (int i = 0; i < d; i++) {                                              \
+        double acc = xc[i] - xp[i] - g[i]; /* h_n */                             \
+        if (n > (lo)) {                                                          \
+          const double* dp = dx + (size_t)(n - 2) * sd;                          \
+          double t = -dp[i];                                                     \
+          for (int q = 0; q < d; q++) t -= Gp[i * d + q] * dp[q];                \
+          acc += t;                                                              \
+        }                                                                        \
+        v[i] = -acc;                                                             \
+      }                                                                          \
+      for (size_t q = 0; q < dd; q++) Gc[q] = -Gc[q];                            \
+      for (int i = 0; i < d; i++) Gc[i * d + i] += 1.0;                          \
+      if (solve_lin(d, Gc, v, 1) != 0) { singular = 1; break; }                  \
+      for (int i = 0; i < d; i++) dn[i] = v[i];                                  \
+    }
+
+  for (k = 0;; k++) {
+    int singular = 0;
+    int64_t lo, hi;
+    double r = 0.0;
+    if (plain) {
+      orc_residual_implicit(method, sys, d, P, dt, T, x0, traj, 1, h);
+      r = norm_inf(h, (size_t)T * sd);
+      if (hist) hist[k] = r;
+      if (!isfinite(r)) { status = ORC_NONFINITE; break; }
+      if (r < tol) { status = ORC_OK; break; }
+      if (k >= max_iter) { status = ORC_NOT_CONVERGED; break; }
+      lo = 1;
+      hi = T;
+    } else {
+      /* first violation at or after p */
+      double hp = 0.0;
+      for (; p <= T; p++) {
+        const double* xp = p == 1 ? x0 : traj + (size_t)(p - 2) * sd;
+        const double* xc = traj + (size_t)(p - 1) * sd;
+        implicit_g(method, sys, d, P, dt, xp, xc, g, NULL, Gc);
+        for (int i = 0; i < d; i++) hs[i] = xc[i] - xp[i] - g[i];
+        for (size_t q = 0; q < dd; q++) Gc[q] = -Gc[q];
+        for (int i = 0; i < d; i++) Gc[i * d + i] += 1.0;
+        if (solve_lin(d, Gc, hs, 1) != 0) { hp = INFINITY; break; }
+        hp = norm_inf(hs, sd);
+        if (!(hp < tol)) break;
+      }
+      if (p > T) { status = ORC_OK; break; }
+      if (!isfinite(hp)) { status = ORC_NONFINITE; break; }
+      if (k >= max_iter) { status = ORC_NOT_CONVERGED; break; }
+      if (hist) hist[k] = hp;
+      lo = p;
+      hi = (window >= T - p + 1) ? T : p + window - 1;
+    }
+    STEP_RANGE(lo, hi)
+    if (singular) { status = ORC_NONFINITE; break; }
+    /* accept below the first non-finite or out-of-guard updated state */
+    int64_t q = hi + 1;
+    if (!plain)
+      for (int64_t n = lo; n <= hi; n++) {
+        int bad = 0;
+        for (int i = 0; i < d; i++) {
+          double val = traj[(size_t)(n - 1) * sd + i] + dx[(size_t)(n - 1) * sd + i];
+          if (!isfinite(val) || fabs(val) > guard) bad = 1;
+        }
+        if (bad) { q = n; break; }
+      }
+    if (q == lo) { status = ORC_NONFINITE; break; }
+    for (int64_t n = lo; n < q; n++)
+      for (int i = 0; i < d; i++) traj[(size_t)(n - 1) * sd + i] += dx[(size_t)(n - 1) * sd + i];
+  }
+  #undef STEP_RANGE
+  if (iters) *iters = k;
+  if (final_resid) {
+    orc_residual_implicit(method, sys, d, P, dt, T, x0, traj, 1, h);
+    *final_resid = norm_inf(h, (size_t)T * sd);
+  }
+  free(h);
+  free(dx);
+  free(g);
+  free(Gp);
+  free(Gc);
+  free(v);
+  free(hs);
   return status;
 }
 
