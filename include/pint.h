@@ -61,6 +61,8 @@ typedef enum { PINT_F64 = 0, PINT_F32 = 1 } pint_dtype;
  *   LORENZ63   d=3                                      theta = (sigma, rho, beta)
  *   LORENZ96   d>=4: f_i = (x_{i+1}-x_{i-2}) x_{i-1} - x_i + F   theta = (F)
  *   KURAMOTO   f_i = w_i + K sum_j sin(x_j - x_i)       theta = (K, w_1..w_d)
+ *   ROBERTSON  d=3: (-k1 y1 + k3 y2 y3, k1 y1 - k2 y2^2 - k3 y2 y3, k2 y2^2)
+ *                                                       theta = (k1, k2, k3)    [Sec. 4.2, eq. robertson]
  */
 typedef enum {
   PINT_SYS_LINEAR = 0,
@@ -69,8 +71,25 @@ typedef enum {
   PINT_SYS_CARTPOLE = 3,
   PINT_SYS_LORENZ63 = 4,
   PINT_SYS_LORENZ96 = 5,
-  PINT_SYS_KURAMOTO = 6
+  PINT_SYS_KURAMOTO = 6,
+  PINT_SYS_ROBERTSON = 7
 } pint_system_id;
+
+/* One-step rule x_n = step(x_{n-1}) whose trajectory is solved for.
+ *   RK4          classic explicit Runge-Kutta, x_n = Phi(x_{n-1})
+ *                (eqs. explicit-ode, explicit-rk); residual
+ *                h_n = x_n - Phi(x_{n-1}) (eq. root-finding-problem).
+ *   BACKWARD_EULER, TRAPEZOIDAL: the implicit rules x_n = x_{n-1} + g with
+ *                g = dt f(x_n) (eq. implicit-euler) or
+ *                g = dt/2 (f(x_{n-1}) + f(x_n)) (Sec. 3.4, eq. implicit-ode).
+ *                Newton's step is eq. newton-step-implicit-recursion; the
+ *                residual the solver tests, reports and returns from
+ *                pint_residual is (I - dg/dx_n)^{-1} (x_n - x_{n-1} - g), the
+ *                quantity the paper reports for its implicit solver
+ *                (Sec. 4.2, Figure 8).  Systems of dimension d <= 4 only
+ *                (the batched small solver); others return
+ *                PINT_ERR_UNSUPPORTED, as does pint_adjoint. */
+typedef enum { PINT_RK4 = 0, PINT_BACKWARD_EULER = 1, PINT_TRAPEZOIDAL = 2 } pint_method;
 
 typedef struct {
   int32_t system;        /* pint_system_id                                      */
@@ -78,6 +97,8 @@ typedef struct {
   int32_t n_params;      /* must equal pint_n_params(system, d)                 */
   int32_t params_shared; /* 1: one theta for every instance; 0: [B][n_params]   */
   const void* params;    /* device pointer, solve dtype                         */
+  int32_t method;        /* pint_method (0, the RK4 rule, when zero-filled)     */
+  int32_t reserved;      /* must be 0                                           */
 } pint_system;
 
 typedef struct {
@@ -136,8 +157,8 @@ size_t pint_workspace_bytes(const pint_system* sys, int64_t B, int64_t T_total,
  * ||h||_inf < tol, otherwise applies the full Newton step.  This is the
  * paper's method.  Windowed mode (window W >= 1, also when W >= T_b), a
  * safeguard the paper does not state: with p the first step whose
- * ||h_p||_inf >= tol, the Newton step is computed from dx_p = -h_p over
- * steps p..min(T_b, p+W-1) only, steps
+ * ||h_p||_inf >= tol, the Newton step is computed from dx_{p-1} = 0 (so
+ * dx_p = -h_p for RK4) over steps p..min(T_b, p+W-1) only, steps
  * before p are left as they are, and the update is accepted only below the
  * first updated state that is non-finite or exceeds `guard`.  Both modes have
  * the same fixed point (the sequential trajectory).
@@ -184,16 +205,21 @@ pint_status pint_graph_launch(pint_graph graph, pint_stream_t stream);
 pint_status pint_graph_destroy(pint_graph graph);
 
 /* pint_seq_integrate — the sequential comparator x_n = Phi(x_{n-1}),
- * n = 1..T_b, for every instance (eq. explicit-ode with classic RK4).
- * T_off as in pint_solve_varlen; traj [T_off[B]][d] is written. */
+ * n = 1..T_b, for every instance (eq. explicit-ode with classic RK4; for an
+ * implicit sys->method each step is solved by Newton's method from
+ * x_{n-1} until the correction is within a few ulps of |x_n|, at most 100
+ * corrections).  T_off as in pint_solve_varlen; traj [T_off[B]][d] is
+ * written. */
 pint_status pint_seq_integrate(const pint_system* sys, int64_t B,
                                const void* x0, double dt, const int64_t* T_off,
                                int64_t T_max, int32_t dtype, void* traj,
                                pint_stream_t stream);
 
 /* pint_residual — h_n = x_n - Phi(x_{n-1}) for every step of a uniform
- * batch (eq. root-finding-problem): h [B][T][d], and hmax [B] (double) the
- * infinity norm per instance (+inf if any entry is non-finite). */
+ * batch (eq. root-finding-problem; the scaled implicit residual of
+ * pint_method for the implicit rules): h [B][T][d] (may be NULL), and
+ * hmax [B] (double) the infinity norm per instance (+inf if any entry is
+ * non-finite). */
 pint_status pint_residual(const pint_system* sys, int64_t B, const void* x0,
                           double dt, int64_t T, int32_t dtype, const void* traj,
                           void* h, double* hmax, pint_stream_t stream);
@@ -201,7 +227,9 @@ pint_status pint_residual(const pint_system* sys, int64_t B, const void* x0,
 /* pint_elements — the Newton-step elements of a uniform batch:
  * A [B][T][d][d] with A_n = dPhi/dx at x_n (n = 0..T-1, x_0 = x0) and
  * b [B][T][d] with b_n = -h_{n+1}, so that dx_{n+1} = A_n dx_n + b_n with
- * dx_0 = 0 (eqs. newton-step-recursion, initialization). */
+ * dx_0 = 0 (eqs. newton-step-recursion, initialization).  For the implicit
+ * rules (eq. newton-step-implicit-recursion), with H = I - dg/dx_{n+1} and
+ * g = g(x_n, x_{n+1}): A_n = H^{-1} (I + dg/dx_n), b_n = -H^{-1} h_{n+1}. */
 pint_status pint_elements(const pint_system* sys, int64_t B, const void* x0,
                           double dt, int64_t T, int32_t dtype,
                           const void* traj, void* A, void* b,

@@ -24,9 +24,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpint.so")
 
 # pint_system_id
-LINEAR, LOGISTIC, VDP, CARTPOLE, LORENZ63, LORENZ96, KURAMOTO = range(7)
+LINEAR, LOGISTIC, VDP, CARTPOLE, LORENZ63, LORENZ96, KURAMOTO, ROBERTSON = range(8)
 SYSTEM_NAMES = {"linear": LINEAR, "logistic": LOGISTIC, "vdp": VDP, "cartpole": CARTPOLE,
-                "lorenz63": LORENZ63, "lorenz96": LORENZ96, "kuramoto": KURAMOTO}
+                "lorenz63": LORENZ63, "lorenz96": LORENZ96, "kuramoto": KURAMOTO,
+                "robertson": ROBERTSON}
+# pint_method: the one-step rule
+RK4, BACKWARD_EULER, TRAPEZOIDAL = range(3)
+METHOD_NAMES = {"rk4": RK4, "backward_euler": BACKWARD_EULER, "trapezoidal": TRAPEZOIDAL}
 # pint_status
 OK, ERR_INVALID_ARG, ERR_DEVICE, ERR_WORKSPACE, NOT_CONVERGED, NONFINITE, ERR_UNSUPPORTED = range(7)
 F64, F32 = 0, 1
@@ -38,7 +42,8 @@ class PintError(RuntimeError):
 
 class pint_system(C.Structure):
     _fields_ = [("system", C.c_int32), ("d", C.c_int32), ("n_params", C.c_int32),
-                ("params_shared", C.c_int32), ("params", C.c_void_p)]
+                ("params_shared", C.c_int32), ("params", C.c_void_p), ("method", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class pint_options(C.Structure):
@@ -141,8 +146,10 @@ def supported(system: int, d: int, dtype: int = F64) -> bool:
     return bool(load().pint_supported(system, d, dtype))
 
 
-def make_system(system: int, d: int, params: torch.Tensor, shared: bool) -> pint_system:
-    return pint_system(system, d, n_params(system, d), 1 if shared else 0, _ptr(params))
+def make_system(system: int, d: int, params: torch.Tensor, shared: bool,
+                method: int = RK4) -> pint_system:
+    return pint_system(system, d, n_params(system, d), 1 if shared else 0, _ptr(params),
+                       _method_id(method), 0)
 
 
 def make_options(dtype: int, tol: float = 1e-10, window: int = 0, max_iter: int = 0,
@@ -155,6 +162,10 @@ def make_options(dtype: int, tol: float = 1e-10, window: int = 0, max_iter: int 
 
 def _sys_id(system) -> int:
     return SYSTEM_NAMES[system] if isinstance(system, str) else int(system)
+
+
+def _method_id(method) -> int:
+    return METHOD_NAMES[method] if isinstance(method, str) else int(method)
 
 
 def _params_2d(params: torch.Tensor, B: int, np_: int):
@@ -261,10 +272,12 @@ def _workspace(nbytes: int, device) -> Optional[torch.Tensor]:
 
 def solve(system, x0: torch.Tensor, params: torch.Tensor, dt: float, T: int, *,
           tol: float = 1e-10, window: int = 0, max_iter: int = 0, guess: Optional[torch.Tensor] = None,
-          guard: float = 1e6, tile: int = 0, stream=None):
+          guard: float = 1e6, tile: int = 0, method=RK4, stream=None):
     """Newton solve of a uniform batch.  x0 [B, d] (or [d]); params [n_params]
-    (shared) or [B, n_params].  Returns (traj [B, T, d], iters [B] int64,
-    resid [B] float64, status [B] int32), all on x0's device."""
+    (shared) or [B, n_params]; method: "rk4", "backward_euler",
+    "trapezoidal" (or the pint_method code).  Returns (traj [B, T, d],
+    iters [B] int64, resid [B] float64, status [B] int32), all on x0's
+    device."""
     sid = _sys_id(system)
     single = x0.dim() == 1
     x0 = (x0[None] if single else x0).contiguous()
@@ -278,7 +291,7 @@ def solve(system, x0: torch.Tensor, params: torch.Tensor, dt: float, T: int, *,
     iters = torch.empty(B, dtype=torch.int64, device=x0.device)
     resid = torch.empty(B, dtype=torch.float64, device=x0.device)
     status = torch.empty(B, dtype=torch.int32, device=x0.device)
-    sysd = make_system(sid, d, prm, shared)
+    sysd = make_system(sid, d, prm, shared, method)
     opts = make_options(dt_code, tol, window, max_iter, 1 if guess is not None else 0, guard, tile)
     ws = _workspace(pint_workspace_bytes(sysd, B, B * T, T, opts), x0.device)
     _check(pint_solve(sysd, B, x0, float(dt), int(T), opts, traj, iters, resid, status, ws, stream),
@@ -298,7 +311,7 @@ def longest_first(lengths, device) -> torch.Tensor:
 def solve_varlen(system, x0: torch.Tensor, params: torch.Tensor, dt: float, lengths, *,
                  tol: float = 1e-10, window: int = 0, max_iter: int = 0, guess=None,
                  guard: float = 1e6, tile: int = 0, block: int = 0, wg_per_cu: int = 0,
-                 order=None, stream=None):
+                 order=None, method=RK4, stream=None):
     """Newton solve of B instances with their own horizons `lengths` [B].
     `order`: None, "longest_first", or a device int64 permutation [B].
     Returns (traj [sum T, d] packed, T_off [B+1], iters, resid, status)."""
@@ -322,7 +335,7 @@ def solve_varlen(system, x0: torch.Tensor, params: torch.Tensor, dt: float, leng
     iters = torch.empty(B, dtype=torch.int64, device=x0.device)
     resid = torch.empty(B, dtype=torch.float64, device=x0.device)
     status = torch.empty(B, dtype=torch.int32, device=x0.device)
-    sysd = make_system(sid, d, prm, shared)
+    sysd = make_system(sid, d, prm, shared, method)
     opts = make_options(_dtype_code(x0), tol, window, max_iter, 1 if guess is not None else 0,
                         guard, tile, block, wg_per_cu, order)
     ws = _workspace(pint_workspace_bytes(sysd, B, total, T_max, opts), x0.device)
@@ -340,7 +353,8 @@ class SolveGraph:
 
     def __init__(self, system, x0: torch.Tensor, params: torch.Tensor, dt: float, lengths, *,
                  tol: float = 1e-10, window: int = 0, max_iter: int = 0, guess: bool = False,
-                 guard: float = 1e6, block: int = 0, wg_per_cu: int = 0, order=None):
+                 guard: float = 1e6, block: int = 0, wg_per_cu: int = 0, order=None,
+                 method=RK4):
         sid = _sys_id(system)
         self.x0 = x0.contiguous().clone()
         B, d = self.x0.shape
@@ -359,7 +373,7 @@ class SolveGraph:
         self.iters = torch.empty(B, dtype=torch.int64, device=x0.device)
         self.resid = torch.empty(B, dtype=torch.float64, device=x0.device)
         self.status = torch.empty(B, dtype=torch.int32, device=x0.device)
-        self._sysd = make_system(sid, d, self.params, shared)
+        self._sysd = make_system(sid, d, self.params, shared, method)
         self._opts = make_options(_dtype_code(x0), tol, window, max_iter, 1 if guess else 0, guard,
                                   0, block, wg_per_cu, order)
         self.ws = _workspace(pint_workspace_bytes(self._sysd, B, total, T_max, self._opts), x0.device)
@@ -386,9 +400,11 @@ class SolveGraph:
             pass
 
 
-def seq_integrate(system, x0: torch.Tensor, params: torch.Tensor, dt: float, lengths, stream=None):
-    """Sequential RK4 comparator.  lengths: int (uniform) or [B].  Returns the
-    packed trajectory [sum T, d] (reshape to [B, T, d] for uniform T)."""
+def seq_integrate(system, x0: torch.Tensor, params: torch.Tensor, dt: float, lengths,
+                  method=RK4, stream=None):
+    """Sequential comparator (RK4, or a per-step Newton solve for the
+    implicit rules).  lengths: int (uniform) or [B].  Returns the packed
+    trajectory [sum T, d] (reshape to [B, T, d] for uniform T)."""
     sid = _sys_id(system)
     x0 = x0.contiguous()
     B, d = x0.shape
@@ -399,15 +415,16 @@ def seq_integrate(system, x0: torch.Tensor, params: torch.Tensor, dt: float, len
     T_off_h = torch.zeros(B + 1, dtype=torch.int64)
     T_off_h[1:] = torch.cumsum(lengths, 0)
     traj = torch.empty((int(T_off_h[-1]), d), dtype=x0.dtype, device=x0.device)
-    sysd = make_system(sid, d, prm, shared)
+    sysd = make_system(sid, d, prm, shared, method)
     _check(pint_seq_integrate(sysd, B, x0, float(dt), T_off_h.to(x0.device),
                               int(lengths.max()) if B else 0, _dtype_code(x0), traj, stream),
            "pint_seq_integrate")
     return traj
 
 
-def residual(system, x0, params, dt, traj, stream=None):
-    """h [B, T, d] and ||h||_inf per instance for a uniform batch."""
+def residual(system, x0, params, dt, traj, method=RK4, stream=None):
+    """h [B, T, d] and ||h||_inf per instance for a uniform batch (the scaled
+    residual for the implicit rules)."""
     sid = _sys_id(system)
     x0 = x0.contiguous()
     B, d = x0.shape
@@ -415,13 +432,13 @@ def residual(system, x0, params, dt, traj, stream=None):
     prm, shared = _params_2d(params.to(x0.dtype), B, n_params(sid, d))
     h = torch.empty_like(traj)
     hmax = torch.empty(B, dtype=torch.float64, device=x0.device)
-    sysd = make_system(sid, d, prm, shared)
+    sysd = make_system(sid, d, prm, shared, method)
     _check(pint_residual(sysd, B, x0, float(dt), T, _dtype_code(x0), traj.contiguous(), h, hmax,
                          stream), "pint_residual")
     return h, hmax
 
 
-def elements(system, x0, params, dt, traj, stream=None):
+def elements(system, x0, params, dt, traj, method=RK4, stream=None):
     """Newton-step elements A [B, T, d, d], b [B, T, d] of a uniform batch."""
     sid = _sys_id(system)
     x0 = x0.contiguous()
@@ -430,7 +447,7 @@ def elements(system, x0, params, dt, traj, stream=None):
     prm, shared = _params_2d(params.to(x0.dtype), B, n_params(sid, d))
     A = torch.empty((B, T, d, d), dtype=x0.dtype, device=x0.device)
     b = torch.empty((B, T, d), dtype=x0.dtype, device=x0.device)
-    sysd = make_system(sid, d, prm, shared)
+    sysd = make_system(sid, d, prm, shared, method)
     _check(pint_elements(sysd, B, x0, float(dt), T, _dtype_code(x0), traj.contiguous(), A, b,
                          stream), "pint_elements")
     return A, b

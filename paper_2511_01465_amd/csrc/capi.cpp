@@ -21,6 +21,7 @@ int n_params_of(int32_t system, int32_t d) {
     case PINT_SYS_LORENZ63: return d == 3 ? 3 : -1;
     case PINT_SYS_LORENZ96: return d >= 4 ? 1 : -1;
     case PINT_SYS_KURAMOTO: return d >= 1 ? d + 1 : -1;
+    case PINT_SYS_ROBERTSON: return d == 3 ? 3 : -1;
   }
   return -1;
 }
@@ -32,8 +33,12 @@ int check_sys(const pint_system* sys, int64_t B) {
   if (n_params_of(sys->system, sys->d) < 0) return PINT_ERR_INVALID_ARG;
   if (sys->n_params != n_params_of(sys->system, sys->d)) return PINT_ERR_INVALID_ARG;
   if (B > 0 && !sys->params) return PINT_ERR_INVALID_ARG;
+  if (sys->method < PINT_RK4 || sys->method > PINT_TRAPEZOIDAL || sys->reserved != 0)
+    return PINT_ERR_INVALID_ARG;
   if (!small_supported(sys->system, sys->d) && !dense_supported(sys->system, sys->d))
     return PINT_ERR_UNSUPPORTED;
+  // the implicit rules are built for the small dimensions only
+  if (sys->method != PINT_RK4 && !small_supported(sys->system, sys->d)) return PINT_ERR_UNSUPPORTED;
   return PINT_OK;
 }
 
@@ -55,6 +60,7 @@ SolveArgs make_args(const pint_system* sys, int64_t B, const void* x0, double dt
   SolveArgs a{};
   a.system = sys->system;
   a.d = sys->d;
+  a.method = sys->method;
   a.dtype = o ? o->dtype : PINT_F64;
   a.B = B;
   a.x0 = x0;
@@ -113,11 +119,11 @@ int pint_supported(int32_t system, int32_t d, int32_t dtype) {
 size_t pint_workspace_bytes(const pint_system* sys, int64_t B, int64_t T_total, int64_t T_max,
                             const pint_options* opts) {
   if (!sys || !opts || B < 0) return 0;
-  if (is_small(sys->system, sys->d)) return small_ws_bytes(B);
   pint_system s = *sys;
   SolveArgs a = make_args(&s, B, nullptr, 0.0, nullptr, T_max, T_max, opts, nullptr, nullptr,
                           nullptr, nullptr, nullptr, 0, nullptr);
   (void)T_total;
+  if (is_small(sys->system, sys->d)) return small_ws_bytes(a);
   return dense_ws_bytes(a);
 }
 
@@ -318,6 +324,7 @@ pint_status pint_adjoint(const pint_system* sys, int64_t B, const void* x0, doub
   if ((dtype != PINT_F64 && dtype != PINT_F32) || T < 0 || seg < 0 || !std::isfinite(dt))
     return PINT_ERR_INVALID_ARG;
   if (sys->system == PINT_SYS_CARTPOLE && dL_dtheta) return PINT_ERR_UNSUPPORTED;
+  if (sys->method != PINT_RK4) return PINT_ERR_UNSUPPORTED;
   if (B == 0) return PINT_OK;
   if (!x0 || !dL_dx0 || (T > 0 && (!traj || !g))) return PINT_ERR_INVALID_ARG;
   pint_options o{};

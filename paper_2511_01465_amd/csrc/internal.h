@@ -10,6 +10,7 @@ namespace pint {
 // Everything a batched solve needs (device pointers unless noted).
 struct SolveArgs {
   int32_t system, d, dtype;
+  int32_t method;         // one-step rule: 0 RK4, 1 backward Euler, 2 trapezoidal
   int64_t B;
   const void* x0;
   const void* params;
@@ -40,7 +41,7 @@ enum { ST_OK = 0, ST_INVALID = 1, ST_DEVICE = 2, ST_WORKSPACE = 3, ST_NOT_CONVER
 bool small_supported(int system, int d);
 bool dense_supported(int system, int d);
 
-size_t small_ws_bytes(int64_t B);
+size_t small_ws_bytes(const SolveArgs& a);
 int small_solve(const SolveArgs& a);
 int small_seq(const SolveArgs& a);
 int small_residual(const SolveArgs& a, void* h, double* hmax);

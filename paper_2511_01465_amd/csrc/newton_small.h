@@ -1,0 +1,615 @@
+// Small state dimension (d <= 4): one workgroup per instance runs the whole
+// Newton loop of Sec. 3.2 (Sec. 3.4 for the implicit rules) on chip —
+// residual, stop test, window search, element construction, affine scan and
+// update — pulling instances from a device work queue, so a batch of any
+// size and mix of horizons is one persistent launch.  Also the sequential
+// comparator and the residual / element kernels used for checking.  Every
+// kernel is templated on the step rule M (StepRule in systems_small.h); the
+// launchers are instantiated per rule in newton_small.hip (RK4) and
+// implicit_small.hip (backward Euler, trapezoidal).
+#pragma once
+
+#include "internal.h"
+#include "systems_small.h"
+
+namespace pint {
+
+struct SmallKArgs {
+  int64_t B;
+  const void* x0;
+  const void* params;
+  int64_t pstride;
+  const int64_t* T_off;
+  int64_t T_uniform;
+  void* traj;
+  double dt, tol, guard;
+  int64_t window, max_iter;
+  int32_t guess;
+  int64_t* iters;
+  double* resid;
+  int32_t* status;
+  uint32_t* queue;
+  const int64_t* order;  // [B] instance taken at each queue slot, or nullptr
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void load_state(const T* X, const T* x0, int64_t n, T* out) {
+  if (n == 0) {
+#pragma unroll
+    for (int i = 0; i < D; i++) out[i] = x0[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < D; i++) out[i] = X[(n - 1) * D + i];
+  }
+}
+
+// Infinity norm of the residual the rule tests at step n (eq.
+// root-finding-problem for RK4), +inf if anything is non-finite.
+template <typename T, class S, int M>
+__device__ __forceinline__ double step_resid(const T* P, T dt, const T* X, const T* x0, int64_t n) {
+  constexpr int D = S::D;
+  T xp[D], xc[D], h[D];
+  load_state<T, D>(X, x0, n - 1, xp);
+  load_state<T, D>(X, x0, n, xc);
+  StepRule<T, S, M>::resid(P, dt, xp, xc, h);
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; i++) m = acc_norm(m, h[i]);
+  return m;
+}
+
+template <typename T, class S, int M, int NT>
+__global__ __launch_bounds__(NT) void k_newton_small(SmallKArgs a) {
+  constexpr int D = S::D, NP = S::NP;
+  __shared__ Aff<T, D> s_aff[NT / PINT_WAVE];
+  __shared__ double s_red[NT / PINT_WAVE];
+  __shared__ int64_t s_redi[NT / PINT_WAVE];
+  __shared__ T s_z[D], s_xprev[D], s_xlast[D], s_zlast[D];
+  __shared__ uint32_t s_slot;
+  __shared__ double s_hp;
+  const int tid = threadIdx.x;
+  const T dt = (T)a.dt;
+
+  for (;;) {
+    if (tid == 0) s_slot = atomicAdd(a.queue, 1u);
+    __syncthreads();
+    const int64_t slot = s_slot;
+    __syncthreads();
+    if (slot >= a.B) break;
+    const int64_t inst = a.order ? a.order[slot] : slot;
+    if (inst < 0 || inst >= a.B) continue;  // not a permutation entry: skipped
+
+    const int64_t t0 = a.T_off ? a.T_off[inst] : inst * a.T_uniform;
+    const int64_t Tn = (a.T_off ? a.T_off[inst + 1] : t0 + a.T_uniform) - t0;
+    T* X = static_cast<T*>(a.traj) + t0 * D;
+    T P[NP], x0[D];
+    {
+      const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
+#pragma unroll
+      for (int i = 0; i < NP; i++) P[i] = Pg[i];
+      const T* xg = static_cast<const T*>(a.x0) + inst * D;
+#pragma unroll
+      for (int i = 0; i < D; i++) x0[i] = xg[i];
+    }
+    if (a.guess == 0)
+      for (int64_t n = tid; n < Tn; n += NT)
+#pragma unroll
+        for (int i = 0; i < D; i++) X[n * D + i] = x0[i];
+    __syncthreads();
+
+    const bool plain = (a.window <= 0);
+    const int64_t W = a.window;
+    int64_t k = 0, p = 1;
+    int st = ST_OK;
+    while (Tn > 0) {
+      int64_t lo, hi;
+      if (plain) {
+        double r = 0.0;
+        for (int64_t c0 = 1; c0 <= Tn; c0 += NT) {
+          const int64_t n = c0 + tid;
+          if (n <= Tn) r = fmax(r, step_resid<T, S, M>(P, dt, X, x0, n));
+        }
+        r = block_max<NT>(r, s_red);
+        if (!(r < INFINITY)) { st = ST_NONFINITE; break; }
+        if (r < a.tol) { st = ST_OK; break; }
+        if (k >= a.max_iter) { st = ST_NOT_CONVERGED; break; }
+        lo = 1;
+        hi = Tn;
+      } else {
+        // first violation at or after p; steps before p are untouched
+        int64_t fv = INT64_MAX;
+        for (int64_t c0 = p; c0 <= Tn; c0 += NT) {
+          const int64_t n = c0 + tid;
+          int64_t v = INT64_MAX;
+          double hn = 0.0;
+          if (n <= Tn) {
+            hn = step_resid<T, S, M>(P, dt, X, x0, n);
+            if (!(hn < a.tol)) v = n;
+          }
+          fv = block_min_i64<NT>(v, s_redi);
+          if (fv != INT64_MAX) {
+            if (n == fv) s_hp = hn;
+            break;
+          }
+        }
+        __syncthreads();
+        if (fv == INT64_MAX) { st = ST_OK; break; }
+        p = fv;
+        const double hp = s_hp;
+        if (!(hp < INFINITY)) { st = ST_NONFINITE; break; }
+        if (k >= a.max_iter) { st = ST_NOT_CONVERGED; break; }
+        lo = p;
+        hi = (W >= Tn - p + 1) ? Tn : p + W - 1;
+      }
+
+      // Newton step over [lo, hi] (eq. newton-step-recursion, or
+      // newton-step-implicit-recursion): the elements of the rule are
+      // scanned chunk by chunk from dx_{lo-1} = 0.
+      if (tid < D) {
+        s_z[tid] = T(0);
+        s_xprev[tid] = (lo == 1) ? x0[tid] : X[(lo - 2) * D + tid];
+      }
+      __syncthreads();
+      int64_t qcut = INT64_MAX;
+      for (int64_t c0 = lo; c0 <= hi; c0 += NT) {
+        const int64_t n = c0 + tid;
+        const bool act = n <= hi;
+        T xc[D];
+        Aff<T, D> e;
+        if (act) {
+          T xp[D];
+          if (tid == 0) {
+#pragma unroll
+            for (int i = 0; i < D; i++) xp[i] = s_xprev[i];
+          } else {
+#pragma unroll
+            for (int i = 0; i < D; i++) xp[i] = X[(n - 2) * D + i];
+          }
+#pragma unroll
+          for (int i = 0; i < D; i++) xc[i] = X[(n - 1) * D + i];
+          StepRule<T, S, M>::element(P, dt, xp, xc, e.A, e.b);
+        } else {
+          aff_identity(e);
+#pragma unroll
+          for (int i = 0; i < D; i++) xc[i] = T(0);
+        }
+        block_scan_aff<T, D, NT>(e, s_aff);
+        T dx[D], xn[D];
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          T acc = e.b[i];
+#pragma unroll
+          for (int j = 0; j < D; j++) acc += e.A[i * D + j] * s_z[j];
+          dx[i] = acc;
+          xn[i] = xc[i] + acc;
+          bad = bad || !finite_(xn[i]) || fabs((double)xn[i]) > a.guard;
+        }
+        int64_t q = INT64_MAX;
+        if (!plain) q = block_min_i64<NT>((act && bad) ? n : INT64_MAX, s_redi);
+        const int64_t last = (hi < c0 + NT - 1) ? hi : c0 + NT - 1;
+        if (n == last) {
+#pragma unroll
+          for (int i = 0; i < D; i++) { s_xlast[i] = xc[i]; s_zlast[i] = dx[i]; }
+        }
+        if (act && n < q) {
+#pragma unroll
+          for (int i = 0; i < D; i++) X[(n - 1) * D + i] = xn[i];
+        }
+        __syncthreads();
+        if (q != INT64_MAX) { qcut = q; break; }
+        if (tid < D) { s_xprev[tid] = s_xlast[tid]; s_z[tid] = s_zlast[tid]; }
+        __syncthreads();
+      }
+      if (qcut == lo) { st = ST_NONFINITE; break; }
+      k++;
+    }
+    __syncthreads();
+    double r = 0.0;
+    for (int64_t n = 1 + tid; n <= Tn; n += NT) r = fmax(r, step_resid<T, S, M>(P, dt, X, x0, n));
+    r = block_max<NT>(r, s_red);
+    if (tid == 0) {
+      a.iters[inst] = k;
+      a.resid[inst] = r;
+      a.status[inst] = st;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------ cooperative variant --
+
+// Per-instance control block of the cooperative small-d solver (64 bytes).
+struct SmallCtl {
+  uint32_t bar_count, bar_gen, err, pad[13];
+};
+static_assert(sizeof(SmallCtl) == 64, "control block size");
+
+// Barrier among the G workgroups of one instance: release fence before
+// arriving, acquire fence after leaving; the wait is bounded (the error word
+// is raised and the wave goes on).
+__device__ __forceinline__ void small_barrier(SmallCtl* c, int G, uint32_t& gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t target = gen + 1;
+    const uint32_t prev = atomicAdd(&c->bar_count, 1u);
+    if (prev == (uint32_t)(G - 1)) {
+      __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      __hip_atomic_store(&c->bar_gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      for (uint64_t it = 0;
+           __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target; it++) {
+        if (it > (1ull << 28)) {
+          atomicOr(&c->err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __threadfence();
+    gen = target;
+  }
+  __syncthreads();
+}
+
+// The paper's plain Newton method (Sec. 3.2 / 3.4) for a few long
+// instances, each spread over G co-resident workgroups (cooperative
+// launch); workgroup g owns the contiguous steps [1 + gL, min(T, (g+1)L)],
+// L = ceil(T / G).  Per iteration:
+//   A. each workgroup evaluates the elements of its steps in registers
+//      (the Jacobians are never stored), their residual maximum and the
+//      composition of its elements, and posts both to its slot;
+//   B. after a barrier every workgroup reads all slots: the global residual
+//      gives the stop decision (the same in every workgroup), the
+//      compositions of the workgroups before it, scanned in LDS, give its
+//      carry-in dx at the start of its range;
+//   C. it re-evaluates its elements, scans them chunk by chunk from the
+//      carry-in and writes x += dx in place (the state before its range is
+//      kept from phase A, so every element sees the old iterate);
+// then a barrier before the next iteration.  Results, iteration counts and
+// status follow k_newton_small's plain mode.
+template <typename T, class S, int M, int NT>
+__global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, SmallCtl* ctl,
+                                                          T* slot_agg, double* slot_r) {
+  constexpr int D = S::D, NP = S::NP, E = D * D + D;
+  __shared__ Aff<T, D> s_aff[NT / PINT_WAVE];
+  __shared__ double s_red[NT / PINT_WAVE];
+  __shared__ T s_z[D], s_xprev[D], s_xlast[D], s_zlast[D], s_xb[D];
+  __shared__ Aff<T, D> s_run;
+  const int tid = threadIdx.x;
+  const int64_t inst = blockIdx.x / G;
+  const int g = (int)(blockIdx.x % G);
+  SmallCtl* c = ctl + inst;
+  T* my_agg = slot_agg + (inst * G) * E;
+  double* my_r = slot_r + inst * G;
+  const T dt = (T)a.dt;
+  const int64_t Tn = a.T_uniform;
+  T* X = static_cast<T*>(a.traj) + inst * Tn * D;
+  T P[NP], x0[D];
+  {
+    const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
+#pragma unroll
+    for (int i = 0; i < NP; i++) P[i] = Pg[i];
+    const T* xg = static_cast<const T*>(a.x0) + inst * D;
+#pragma unroll
+    for (int i = 0; i < D; i++) x0[i] = xg[i];
+  }
+  const int64_t L = (Tn + G - 1) / G;
+  const int64_t lo = 1 + (int64_t)g * L;
+  const int64_t hi = (int64_t)(g + 1) * L < Tn ? (int64_t)(g + 1) * L : Tn;  // empty when lo > hi
+  uint32_t gen = 0;
+  if (a.guess == 0)
+    for (int64_t n = lo + tid; n <= hi; n += NT)
+#pragma unroll
+      for (int i = 0; i < D; i++) X[(n - 1) * D + i] = x0[i];
+  small_barrier(c, G, gen);  // the initial iterate is written everywhere
+
+  int64_t k = 0;
+  int st = ST_OK;
+  double rg = 0.0;
+  for (;;) {
+    // ---- A: residual maximum and composition of this workgroup's elements
+    if (tid < D) {
+      // x_{lo-1}: x0, or the last state of the range before (index clamped
+      // into the trajectory, so no load is ever formed outside it)
+      const int64_t jb = (lo >= 2 && lo <= hi) ? lo - 2 : 0;
+      const T xv = X[jb * D + tid];
+      const T* xg = static_cast<const T*>(a.x0) + inst * D;
+      s_xb[tid] = (lo == 1 || lo > hi) ? xg[tid] : xv;
+    }
+    if (tid == 0) aff_identity(s_run);
+    __syncthreads();
+    double r = 0.0;
+    for (int64_t c0 = lo; c0 <= hi; c0 += NT) {
+      const int64_t n = c0 + tid;
+      Aff<T, D> e;
+      if (n <= hi) {
+        T xp[D], xc[D];
+        const T* xq = X + (n >= 2 ? n - 2 : 0) * D;  // x_{n-1} when n > lo
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          xp[i] = (n == lo) ? s_xb[i] : xq[i];
+          xc[i] = X[(n - 1) * D + i];
+        }
+        StepRule<T, S, M>::element(P, dt, xp, xc, e.A, e.b);
+#pragma unroll
+        for (int i = 0; i < D; i++) r = acc_norm(r, e.b[i]);  // |b_n| is the tested residual
+      } else {
+        aff_identity(e);
+      }
+      block_scan_aff<T, D, NT>(e, s_aff);
+      if (tid == NT - 1) {
+        Aff<T, D> run = s_run;
+        aff_after(e, run);  // this chunk after everything before it
+        s_run = e;
+      }
+      __syncthreads();
+    }
+    r = block_max<NT>(r, s_red);
+    if (tid < D * D) my_agg[g * E + tid] = s_run.A[tid];
+    if (tid < D) my_agg[g * E + D * D + tid] = s_run.b[tid];
+    if (tid == 0) my_r[g] = r;
+    small_barrier(c, G, gen);
+
+    // ---- B: global residual and stop test; carry-in from the earlier ranges
+    double rr = 0.0;
+    for (int j = tid; j < G; j += NT) rr = fmax(rr, my_r[j]);
+    rg = block_max<NT>(rr, s_red);
+    if (!(rg < INFINITY)) { st = ST_NONFINITE; break; }
+    if (rg < a.tol) { st = ST_OK; break; }
+    if (k >= a.max_iter) { st = ST_NOT_CONVERGED; break; }
+    {
+      // aggregates 0..g-1 in order: thread t folds a contiguous run of them,
+      // then a block scan; the composed map applied to dx = 0 is its b-part
+      const int q = (g + NT - 1) / NT;
+      Aff<T, D> e;
+      aff_identity(e);
+      for (int j = tid * q; j < (tid + 1) * q && j < g; j++) {
+        Aff<T, D> f;
+#pragma unroll
+        for (int i = 0; i < D * D; i++) f.A[i] = my_agg[j * E + i];
+#pragma unroll
+        for (int i = 0; i < D; i++) f.b[i] = my_agg[j * E + D * D + i];
+        aff_after(f, e);
+        e = f;
+      }
+      block_scan_aff<T, D, NT>(e, s_aff);
+      if (tid == NT - 1) {
+#pragma unroll
+        for (int i = 0; i < D; i++) s_z[i] = e.b[i];
+      }
+      if (tid < D) s_xprev[tid] = s_xb[tid];
+      __syncthreads();
+    }
+
+    // ---- C: the update over this workgroup's range
+    for (int64_t c0 = lo; c0 <= hi; c0 += NT) {
+      const int64_t n = c0 + tid;
+      const bool act = n <= hi;
+      T xc[D];
+      Aff<T, D> e;
+      if (act) {
+        T xp[D];
+        const T* xq = X + (n >= 2 ? n - 2 : 0) * D;  // x_{n-1} when tid > 0
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          xp[i] = (tid == 0) ? s_xprev[i] : xq[i];
+          xc[i] = X[(n - 1) * D + i];
+        }
+        StepRule<T, S, M>::element(P, dt, xp, xc, e.A, e.b);
+      } else {
+        aff_identity(e);
+#pragma unroll
+        for (int i = 0; i < D; i++) xc[i] = T(0);
+      }
+      block_scan_aff<T, D, NT>(e, s_aff);
+      T dx[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        T acc = e.b[i];
+#pragma unroll
+        for (int j = 0; j < D; j++) acc += e.A[i * D + j] * s_z[j];
+        dx[i] = acc;
+      }
+      const int64_t last = (hi < c0 + NT - 1) ? hi : c0 + NT - 1;
+      if (n == last) {
+#pragma unroll
+        for (int i = 0; i < D; i++) { s_xlast[i] = xc[i]; s_zlast[i] = dx[i]; }
+      }
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < D; i++) X[(n - 1) * D + i] = xc[i] + dx[i];
+      }
+      __syncthreads();
+      if (tid < D) { s_xprev[tid] = s_xlast[tid]; s_z[tid] = s_zlast[tid]; }
+      __syncthreads();
+    }
+    small_barrier(c, G, gen);
+    k++;
+  }
+  if (g == 0 && tid == 0) {
+    a.iters[inst] = k;
+    a.resid[inst] = rg;
+    a.status[inst] = st;
+  }
+}
+
+// Sequential comparator: one thread per instance, x_n from x_{n-1} by the
+// rule's own step (RK4, or a converged per-step Newton solve).
+template <typename T, class S, int M>
+__global__ void k_seq_small(SmallKArgs a) {
+  constexpr int D = S::D, NP = S::NP;
+  const int64_t inst = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (inst >= a.B) return;
+  const int64_t t0 = a.T_off ? a.T_off[inst] : inst * a.T_uniform;
+  const int64_t Tn = (a.T_off ? a.T_off[inst + 1] : t0 + a.T_uniform) - t0;
+  T* X = static_cast<T*>(a.traj) + t0 * D;
+  T P[NP], x[D], y[D];
+  const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
+#pragma unroll
+  for (int i = 0; i < NP; i++) P[i] = Pg[i];
+  const T* xg = static_cast<const T*>(a.x0) + inst * D;
+#pragma unroll
+  for (int i = 0; i < D; i++) x[i] = xg[i];
+  const T dt = (T)a.dt;
+  for (int64_t n = 0; n < Tn; n++) {
+    StepRule<T, S, M>::advance(P, dt, x, y);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      x[i] = y[i];
+      X[n * D + i] = y[i];
+    }
+  }
+}
+
+// The rule's residual for every (instance, step) of a uniform batch, and
+// the per-instance max.
+template <typename T, class S, int M>
+__global__ void k_residual_small(SmallKArgs a, T* h, double* hmax) {
+  constexpr int D = S::D, NP = S::NP;
+  const int64_t total = a.B * a.T_uniform;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t inst = g / a.T_uniform, n = g % a.T_uniform + 1;
+    const T* X = static_cast<const T*>(a.traj) + inst * a.T_uniform * D;
+    const T* x0 = static_cast<const T*>(a.x0) + inst * D;
+    T P[NP], xp[D], xc[D], hv[D];
+    const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
+#pragma unroll
+    for (int i = 0; i < NP; i++) P[i] = Pg[i];
+    load_state<T, D>(X, x0, n - 1, xp);
+    load_state<T, D>(X, x0, n, xc);
+    StepRule<T, S, M>::resid(P, (T)a.dt, xp, xc, hv);
+    double m = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      if (h) h[g * D + i] = hv[i];
+      m = acc_norm(m, hv[i]);
+    }
+    atomic_max_nonneg(hmax + inst, m);
+  }
+}
+
+// Elements (A_n, b_n) of the step from x_n to x_{n+1}, n = 0..T-1.
+template <typename T, class S, int M>
+__global__ void k_elements_small(SmallKArgs a, T* A, T* b) {
+  constexpr int D = S::D, NP = S::NP;
+  const int64_t total = a.B * a.T_uniform;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t inst = g / a.T_uniform, n = g % a.T_uniform;
+    const T* X = static_cast<const T*>(a.traj) + inst * a.T_uniform * D;
+    const T* x0 = static_cast<const T*>(a.x0) + inst * D;
+    T P[NP], xn[D], xnext[D], J[D * D], bv[D];
+    const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
+#pragma unroll
+    for (int i = 0; i < NP; i++) P[i] = Pg[i];
+    load_state<T, D>(X, x0, n, xn);
+    load_state<T, D>(X, x0, n + 1, xnext);
+    StepRule<T, S, M>::element(P, (T)a.dt, xn, xnext, J, bv);
+#pragma unroll
+    for (int i = 0; i < D * D; i++) A[g * D * D + i] = J[i];
+#pragma unroll
+    for (int i = 0; i < D; i++) b[g * D + i] = bv[i];
+  }
+}
+
+// ------------------------------------------------------------- dispatch --
+
+template <typename T, typename F>
+int dispatch_small_sys(int system, int d, F&& f) {
+  switch (system) {
+    case 0:
+      switch (d) {
+        case 1: return f(SysLinear<T, 1>{});
+        case 2: return f(SysLinear<T, 2>{});
+        case 3: return f(SysLinear<T, 3>{});
+        case 4: return f(SysLinear<T, 4>{});
+      }
+      break;
+    case 1: if (d == 1) return f(SysLogistic<T>{}); break;
+    case 2: if (d == 2) return f(SysVdP<T>{}); break;
+    case 3: if (d == 4) return f(SysCartPole<T>{}); break;
+    case 4: if (d == 3) return f(SysLorenz63<T>{}); break;
+    case 7: if (d == 3) return f(SysRobertson<T>{}); break;
+  }
+  return ST_UNSUPPORTED;
+}
+
+template <typename F>
+int dispatch_small(int dtype, int system, int d, F&& f) {
+  if (dtype == 0) return dispatch_small_sys<double>(system, d, [&](auto s) { return f((double)0, s); });
+  if (dtype == 1) return dispatch_small_sys<float>(system, d, [&](auto s) { return f((float)0, s); });
+  return ST_UNSUPPORTED;
+}
+
+// One launch of the small-d kernels for rule M; which kernel by `op`.
+enum SmallOp { OP_SOLVE = 0, OP_SEQ = 1, OP_RESIDUAL = 2, OP_ELEMENTS = 3, OP_COOP = 4,
+               OP_COOP_OCCUPANCY = 5 };
+
+constexpr int NT_COOP = 256;  // threads per workgroup of the cooperative solver
+
+struct SmallLaunch {
+  int op, dtype, system, d;
+  int grid, block;
+  hipStream_t stream;
+  void* out0;      // residual: h; elements: A; coop: slot aggregates
+  void* out1;      // elements: b; coop: slot residuals (double)
+  double* hmax;    // residual
+  SmallCtl* ctl;   // coop: control blocks
+  int G;           // coop: workgroups per instance
+  int* occupancy;  // coop occupancy query: resident workgroups per CU
+};
+
+template <int M>
+int small_launch(const SmallKArgs& k, const SmallLaunch& l) {
+  return dispatch_small(l.dtype, l.system, l.d, [&](auto t, auto s) -> int {
+    using T = decltype(t);
+    using S = decltype(s);
+    switch (l.op) {
+      case OP_SOLVE:
+        switch (l.block) {
+          case 64: hipLaunchKernelGGL((k_newton_small<T, S, M, 64>), dim3(l.grid), dim3(64), 0, l.stream, k); break;
+          case 128: hipLaunchKernelGGL((k_newton_small<T, S, M, 128>), dim3(l.grid), dim3(128), 0, l.stream, k); break;
+          case 256: hipLaunchKernelGGL((k_newton_small<T, S, M, 256>), dim3(l.grid), dim3(256), 0, l.stream, k); break;
+          default: return ST_INVALID;
+        }
+        break;
+      case OP_SEQ:
+        hipLaunchKernelGGL((k_seq_small<T, S, M>), dim3(l.grid), dim3(l.block), 0, l.stream, k);
+        break;
+      case OP_RESIDUAL:
+        hipLaunchKernelGGL((k_residual_small<T, S, M>), dim3(l.grid), dim3(l.block), 0, l.stream, k,
+                           static_cast<T*>(l.out0), l.hmax);
+        break;
+      case OP_ELEMENTS:
+        hipLaunchKernelGGL((k_elements_small<T, S, M>), dim3(l.grid), dim3(l.block), 0, l.stream, k,
+                           static_cast<T*>(l.out0), static_cast<T*>(l.out1));
+        break;
+      case OP_COOP_OCCUPANCY:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                   l.occupancy, k_newton_small_coop<T, S, M, NT_COOP>, NT_COOP, 0) == hipSuccess
+                   ? ST_OK : ST_DEVICE;
+      case OP_COOP: {
+        SmallKArgs kk = k;
+        int G = l.G;
+        SmallCtl* ctl = l.ctl;
+        T* agg = static_cast<T*>(l.out0);
+        double* rs = static_cast<double*>(l.out1);
+        void* args[] = {&kk, &G, &ctl, &agg, &rs};
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_newton_small_coop<T, S, M, NT_COOP>),
+                                          dim3(l.grid), dim3(NT_COOP), args, 0, l.stream) == hipSuccess
+                   ? ST_OK : ST_DEVICE;
+      }
+      default: return ST_INVALID;
+    }
+    return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
+  });
+}
+
+// Launchers of the implicit rules (implicit_small.hip).
+int small_launch_implicit(int method, const SmallKArgs& k, const SmallLaunch& l);
+
+}  // namespace pint

@@ -1,5 +1,6 @@
 // Vector fields of small state dimension (d <= 4), evaluated per thread in
-// registers, and the classic RK4 step with its exact derivatives.
+// registers, the classic RK4 step with its exact derivatives, and the step
+// rules (explicit RK4, backward Euler, trapezoidal) the small solver runs.
 #pragma once
 
 #include "device_common.h"
@@ -129,6 +130,26 @@ struct SysLorenz63 {
   }
 };
 
+template <typename T>
+struct SysRobertson {  // Robertson's reaction system (Sec. 4.2, eq. robertson), P = (k1, k2, k3)
+  static constexpr int D = 3, NP = 3;
+  __device__ static void f(const T* P, const T* x, T* out) {
+    out[0] = -P[0] * x[0] + P[2] * x[1] * x[2];
+    out[1] = P[0] * x[0] - P[1] * x[1] * x[1] - P[2] * x[1] * x[2];
+    out[2] = P[1] * x[1] * x[1];
+  }
+  __device__ static void jf(const T* P, const T* x, T* J) {
+    J[0] = -P[0]; J[1] = P[2] * x[2];                        J[2] = P[2] * x[1];
+    J[3] = P[0];  J[4] = T(-2) * P[1] * x[1] - P[2] * x[2];  J[5] = -P[2] * x[1];
+    J[6] = T(0);  J[7] = T(2) * P[1] * x[1];                 J[8] = T(0);
+  }
+  __device__ static void fth(const T*, const T* x, T* G) {
+    G[0] = -x[0]; G[1] = T(0);           G[2] = x[1] * x[2];
+    G[3] = x[0];  G[4] = -x[1] * x[1];   G[5] = -x[1] * x[2];
+    G[6] = T(0);  G[7] = x[1] * x[1];    G[8] = T(0);
+  }
+};
+
 // ---------------------------------------------------------------- RK4 -----
 
 // Classic RK4 (eq. explicit-rk with c = (0, 1/2, 1/2, 1),
@@ -252,5 +273,173 @@ __device__ __forceinline__ void rk4_jac_ptheta(const T* P, T dt, const T* x, T* 
 #pragma unroll
   for (int i = 0; i < D * NP; i++) Sth[i] = c6 * Sacc[i];
 }
+
+// ------------------------------------------------------ step rules -----
+
+// Methods of the one-step map (the public pint_method numbering).
+enum { METHOD_RK4 = 0, METHOD_BEULER = 1, METHOD_TRAP = 2 };
+
+// Solve M X = R in registers for a D x D matrix M and NR right-hand sides
+// (both row-major, overwritten; X is left in R).  Gaussian elimination with
+// partial pivoting; every index is a compile-time constant, so a row
+// exchange is a run of selects (a larger candidate is swapped into the pivot
+// row as it is met, which leaves the column's largest entry there).  A zero
+// pivot yields non-finite results, which the callers report.
+template <typename T, int D, int NR>
+__device__ __forceinline__ void solve_small(T* M, T* R) {
+#pragma unroll
+  for (int c = 0; c < D; c++) {
+#pragma unroll
+    for (int r = c + 1; r < D; r++) {
+      const bool sw = fabs(M[r * D + c]) > fabs(M[c * D + c]);
+#pragma unroll
+      for (int k = c; k < D; k++) {
+        const T u = M[c * D + k], v = M[r * D + k];
+        M[c * D + k] = sw ? v : u;
+        M[r * D + k] = sw ? u : v;
+      }
+#pragma unroll
+      for (int k = 0; k < NR; k++) {
+        const T u = R[c * NR + k], v = R[r * NR + k];
+        R[c * NR + k] = sw ? v : u;
+        R[r * NR + k] = sw ? u : v;
+      }
+    }
+#pragma unroll
+    for (int r = c + 1; r < D; r++) {
+      const T l = M[r * D + c] / M[c * D + c];
+#pragma unroll
+      for (int k = c + 1; k < D; k++) M[r * D + k] -= l * M[c * D + k];
+#pragma unroll
+      for (int k = 0; k < NR; k++) R[r * NR + k] -= l * R[c * NR + k];
+    }
+  }
+#pragma unroll
+  for (int c = D - 1; c >= 0; c--)
+#pragma unroll
+    for (int k = 0; k < NR; k++) {
+      T acc = R[c * NR + k];
+#pragma unroll
+      for (int q = c + 1; q < D; q++) acc -= M[c * D + q] * R[q * NR + k];
+      R[c * NR + k] = acc / M[c * D + c];
+    }
+}
+
+// A step rule supplies, for the step from x_{n-1} = xp to x_n = xc:
+//   resid(P, dt, xp, xc, h)        the residual vector the solver tests;
+//   element(P, dt, xp, xc, A, b)   the Newton-step element, dx_n = A dx_{n-1} + b;
+//   advance(P, dt, xp, xn)         one step of the sequential integrator.
+template <typename T, class S, int M>
+struct StepRule;
+
+// Explicit RK4 (eqs. root-finding-problem, newton-step-recursion):
+// h_n = x_n - Phi(x_{n-1}), A = dPhi/dx(x_{n-1}), b = -h_n.
+template <typename T, class S>
+struct StepRule<T, S, METHOD_RK4> {
+  static constexpr int D = S::D;
+  __device__ static void resid(const T* P, T dt, const T* xp, const T* xc, T* h) {
+    T phi[D];
+    rk4_phi<T, S>(P, dt, xp, phi);
+#pragma unroll
+    for (int i = 0; i < D; i++) h[i] = xc[i] - phi[i];
+  }
+  __device__ static void element(const T* P, T dt, const T* xp, const T* xc, T* A, T* b) {
+    T phi[D];
+    rk4_phi_jac<T, S>(P, dt, xp, phi, A);
+#pragma unroll
+    for (int i = 0; i < D; i++) b[i] = phi[i] - xc[i];
+  }
+  __device__ static void advance(const T* P, T dt, const T* xp, T* xn) { rk4_phi<T, S>(P, dt, xp, xn); }
+};
+
+// Implicit rules x_n = x_{n-1} + g(x_{n-1}, x_n) (Sec. 3.4, eq. implicit-ode):
+// backward Euler g = dt f(x_n); trapezoidal g = dt/2 (f(x_{n-1}) + f(x_n)).
+// With H = I - dg/dx_n (the diagonal block of eq. jacobian-implicit) and
+// h_n = x_n - x_{n-1} - g, the Newton step of eq.
+// newton-step-implicit-recursion is dx_n = H^{-1}(I + dg/dx_{n-1}) dx_{n-1}
+// - H^{-1} h_n.  The residual tested is H^{-1} h_n: the quantity the paper
+// reports for its implicit solver (its Dahlquist value from the zero guess is
+// 1/(1 + dt), not |h_1| = 1).
+template <typename T, class S, int M>
+struct StepRule {
+  static_assert(M == METHOD_BEULER || M == METHOD_TRAP, "unknown step rule");
+  static constexpr int D = S::D;
+  // h (unscaled), H = I - dg/dx_n, and with WANT_GP, Gp = dg/dx_{n-1}.
+  template <bool WANT_GP>
+  __device__ static void parts(const T* P, T dt, const T* xp, const T* xc, T* h, T* H, T* Gp) {
+    T fc[D];
+    S::f(P, xc, fc);
+    S::jf(P, xc, H);
+    if constexpr (M == METHOD_BEULER) {
+#pragma unroll
+      for (int i = 0; i < D; i++) h[i] = xc[i] - xp[i] - dt * fc[i];
+#pragma unroll
+      for (int q = 0; q < D * D; q++) H[q] = -dt * H[q];
+      if constexpr (WANT_GP) {
+#pragma unroll
+        for (int q = 0; q < D * D; q++) Gp[q] = T(0);
+      }
+    } else {
+      const T h2 = T(0.5) * dt;
+      T fp[D];
+      S::f(P, xp, fp);
+#pragma unroll
+      for (int i = 0; i < D; i++) h[i] = xc[i] - xp[i] - (h2 * fp[i] + h2 * fc[i]);
+#pragma unroll
+      for (int q = 0; q < D * D; q++) H[q] = -h2 * H[q];
+      if constexpr (WANT_GP) {
+        S::jf(P, xp, Gp);
+#pragma unroll
+        for (int q = 0; q < D * D; q++) Gp[q] = h2 * Gp[q];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) H[i * D + i] += T(1);
+  }
+  __device__ static void resid(const T* P, T dt, const T* xp, const T* xc, T* h) {
+    T H[D * D];
+    parts<false>(P, dt, xp, xc, h, H, nullptr);
+    solve_small<T, D, 1>(H, h);
+  }
+  __device__ static void element(const T* P, T dt, const T* xp, const T* xc, T* A, T* b) {
+    constexpr int NR = D + 1;
+    T h[D], H[D * D], Gp[D * D], R[D * NR];
+    parts<true>(P, dt, xp, xc, h, H, Gp);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+#pragma unroll
+      for (int j = 0; j < D; j++) R[i * NR + j] = Gp[i * D + j] + (i == j ? T(1) : T(0));
+      R[i * NR + D] = -h[i];
+    }
+    solve_small<T, D, NR>(H, R);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+#pragma unroll
+      for (int j = 0; j < D; j++) A[i * D + j] = R[i * NR + j];
+      b[i] = R[i * NR + D];
+    }
+  }
+  // Sequential step: Newton's method on x_n - xp - g(xp, x_n) = 0 from
+  // x_n = xp, until the correction is within a few ulps of |x_n| (at most
+  // 100 corrections).
+  __device__ static void advance(const T* P, T dt, const T* xp, T* xn) {
+    const T stop = sizeof(T) == 8 ? T(4 * 2.220446049250313e-16) : T(32 * 1.1920929e-7);
+#pragma unroll
+    for (int i = 0; i < D; i++) xn[i] = xp[i];
+    for (int it = 0; it < 100; it++) {
+      T h[D], H[D * D];
+      parts<false>(P, dt, xp, xn, h, H, nullptr);
+      solve_small<T, D, 1>(H, h);
+      T dn = T(0), yn = T(0);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        xn[i] -= h[i];
+        dn = fmax(dn, fabs(h[i]));
+        yn = fmax(yn, fabs(xn[i]));
+      }
+      if (!(dn > stop * yn)) break;  // also ends on a non-finite correction
+    }
+  }
+};
 
 }  // namespace pint

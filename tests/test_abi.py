@@ -56,25 +56,55 @@ def test_host_side_queries_without_gpu():
     assert rc == P.OK   # empty batch: nothing to do
 
 
-def test_options_layout_matches_the_header(tmp_path):
-    """The ctypes mirror of pint_options has the C layout (size and field
-    offsets from a program compiled against include/pint.h)."""
+@pytest.mark.parametrize("struct", ["pint_options", "pint_system"])
+def test_struct_layout_matches_the_header(tmp_path, struct):
+    """The ctypes mirrors of pint_options and pint_system have the C layout
+    (size and field offsets from a program compiled against include/pint.h)."""
     import shutil
     import subprocess
     if not shutil.which("gcc"):
         pytest.skip("no C compiler")
     import paper_2511_01465_amd as P
+    cls = getattr(P, struct)
     src = tmp_path / "layout.c"
-    fields = [f[0] for f in P.pint_options._fields_]
-    body = " ".join('printf("%%zu ", offsetof(pint_options, %s));' % f for f in fields)
+    fields = [f[0] for f in cls._fields_]
+    body = " ".join('printf("%%zu ", offsetof(%s, %s));' % (struct, f) for f in fields)
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pint.h"\n'
-                   'int main(void){printf("%%zu ", sizeof(pint_options)); %s return 0;}\n' % body)
+                   'int main(void){printf("%%zu ", sizeof(%s)); %s return 0;}\n' % (struct, body))
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
-    want = [ctypes.sizeof(P.pint_options)] + [getattr(P.pint_options, f).offset for f in fields]
+    want = [ctypes.sizeof(cls)] + [getattr(cls, f).offset for f in fields]
     assert got == want
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpint.so not built")
+def test_step_rule_argument_checks():
+    """The one-step rule is checked on the host: unknown codes and a non-zero
+    reserved word are invalid; the implicit rules exist for the small
+    dimensions only and not for the adjoint."""
+    import paper_2511_01465_amd as P
+    lib = P.load()
+    assert P.n_params(P.ROBERTSON, 3) == 3 and P.n_params(P.ROBERTSON, 2) == -1
+    assert P.supported(P.ROBERTSON, 3)
+    opts = P.make_options(P.F64)
+
+    def solve_rc(system, d, method, reserved=0):
+        sysd = P.pint_system(system, d, P.n_params(system, d), 1, None, method, reserved)
+        return lib.pint_solve(ctypes.byref(sysd), 0, None, 1e-2, 16, ctypes.byref(opts),
+                              None, None, None, None, None, 0, None)
+
+    assert solve_rc(P.VDP, 2, P.BACKWARD_EULER) == P.OK
+    assert solve_rc(P.ROBERTSON, 3, P.TRAPEZOIDAL) == P.OK
+    assert solve_rc(P.VDP, 2, 3) == P.ERR_INVALID_ARG
+    assert solve_rc(P.VDP, 2, -1) == P.ERR_INVALID_ARG
+    assert solve_rc(P.VDP, 2, P.RK4, reserved=1) == P.ERR_INVALID_ARG
+    assert solve_rc(P.LORENZ96, 40, P.BACKWARD_EULER) == P.ERR_UNSUPPORTED
+    assert solve_rc(P.KURAMOTO, 64, P.TRAPEZOIDAL) == P.ERR_UNSUPPORTED
+    sysd = P.pint_system(P.VDP, 2, 1, 1, None, P.BACKWARD_EULER, 0)
+    assert lib.pint_adjoint(ctypes.byref(sysd), 0, None, 1e-2, 16, P.F64, None, None, None,
+                            None, 0, None, 0, None) == P.ERR_UNSUPPORTED
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libpint.so not built")

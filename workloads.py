@@ -14,7 +14,9 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-LINEAR, LOGISTIC, VDP, CARTPOLE, LORENZ63, LORENZ96, KURAMOTO = range(7)
+LINEAR, LOGISTIC, VDP, CARTPOLE, LORENZ63, LORENZ96, KURAMOTO, ROBERTSON = range(8)
+# One-step rules (public numbering).
+RK4, BACKWARD_EULER, TRAPEZOIDAL = range(3)
 
 
 @dataclass
@@ -151,6 +153,32 @@ def random_band_affine(N: int, d: int, bw: int, boff: int, seed: int = 0):
     band = np.take_along_axis(A, np.broadcast_to(idx, (N, d, bw)), axis=2)
     b = r.normal(0.0, 1.0, size=(N, d))
     return A, band, b
+
+
+def implicit_pins():
+    """The two implicit problems of the paper's Sec. 4.2 (backward Euler,
+    zero initial guess): Dahlquist (lambda = -1 on [0, 4]) and Robertson
+    (k = (0.04, 3e7, 1e4) on [0, 500]); T = horizon / dt."""
+    return [
+        dict(name="dahlquist", system=LINEAR, params=[-1.0], x0=[1.0], horizon=4.0,
+             dts=[1e-1, 1e-2, 1e-3, 1e-4]),
+        dict(name="robertson", system=ROBERTSON, params=[0.04, 3e7, 1e4], x0=[1.0, 0.0, 0.0],
+             horizon=500.0, dts=[1e-1, 1e-2, 5e-3]),
+    ]
+
+
+def robertson_batch(B: int = 1024, seed: int = 6, t_lo: int = 1000, t_hi: int = 5000,
+                    window: int = 0) -> Workload:
+    """Robertson instances around the paper's rates: k1, k2, k3 each times
+    a log-uniform factor in [1/2, 2]; x0 = (1 - s, s, 0) with s ~ U[0, 1e-5];
+    T ~ U{t_lo..t_hi} inclusive; dt = 0.1 (backward Euler)."""
+    r = _rng(seed)
+    base = np.array([0.04, 3e7, 1e4])
+    params = base * np.exp(r.uniform(-math.log(2.0), math.log(2.0), size=(B, 3)))
+    s = r.uniform(0.0, 1e-5, size=B)
+    x0 = np.stack([1.0 - s, s, np.zeros(B)], axis=1)
+    T = r.integers(t_lo, t_hi, size=B, endpoint=True).astype(np.int64)
+    return Workload("robertson_batch", ROBERTSON, 3, 0.1, x0, params, T, window=window)
 
 
 def paper_pins():
