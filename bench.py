@@ -181,6 +181,81 @@ def leg_vdp_batch(P, torch, dev, stream, reps=3, window=256):
     return out
 
 
+# The paper's runtime problems (Sec. 4.1, Figure 4; Sec. 4.2, Figure 7):
+# a fixed horizon split into T steps, one instance, the paper's initial
+# guesses, plain Newton at the tolerance reading 3e-14.  Its A100 times (JAX)
+# for the largest T of each problem, as context only.
+PAPER_RUNTIME = [
+    # name, system, method, params, x0, guess, horizon, T list, paper (T, Newton s, sequential s)
+    ("logistic", 1, 0, [1.0, 1.0], [0.1], 1.0, 10.0, [1000, 10000, 100000, 1000000],
+     (1000000, 0.00331168, 8.27522111)),
+    ("vdp", 2, 0, [1.0], [0.0, 1.0], 1.0, 10.0, [1000, 10000, 100000, 1000000],
+     (1000000, 0.0343277, 9.93280284)),
+    ("cartpole", 3, 0, [9.81, 0.5, 10.0, 1.0], [0.0, 1.5707963267948966, 0.0, 0.0], 0.0, 4.0,
+     [400, 4000, 40000, 400000], (400000, 0.03394353, 8.79305544)),
+    ("dahlquist", 0, 1, [-1.0], [1.0], 0.0, 4.0, [40, 400, 4000, 40000],
+     (40000, 0.00081491, 3.21991856)),
+    ("robertson", 7, 1, [0.04, 3e7, 1e4], [1.0, 0.0, 0.0], 0.0, 500.0, [5000, 50000, 100000],
+     (100000, 0.03630676, 13.69847407)),
+]
+
+
+def leg_paper_runtime(P, torch, dev, stream, reps=2):
+    """Each problem of PAPER_RUNTIME at each T: the Newton solve (the
+    cooperative multi-workgroup launch for long horizons) and the sequential
+    GPU integrator of the same rule, with K = updates + 1."""
+    out = {}
+    for name, sysid, method, prm, x0l, gval, horizon, Ts, paper in PAPER_RUNTIME:
+        rows = []
+        x0 = torch.tensor(x0l, dtype=torch.float64, device=dev)
+        pr = torch.tensor(prm, dtype=torch.float64, device=dev)
+        for T in Ts:
+            dt = horizon / T
+            guess = torch.full((T, len(x0l)), gval, dtype=torch.float64, device=dev)
+            res = {}
+
+            def run():
+                res["o"] = P.solve(sysid, x0, pr, dt, T, tol=3e-14, max_iter=60, guess=guess,
+                                   method=method, stream=stream)
+
+            ms = _time(run, reps, stream)
+            traj, iters, resid, status = res["o"]
+            ms_seq = _time(lambda: P.seq_integrate(sysid, x0[None], pr, dt, T, method=method,
+                                                   stream=stream), 1, stream)
+            rows.append({"T": T, "dt": dt, "K": int(iters) + 1, "status": int(status),
+                         "resid": float(resid), "newton_ms": ms, "sequential_ms": ms_seq,
+                         "speedup_of_newton": ms_seq / ms})
+        out[name] = {"method": ["rk4", "backward_euler", "trapezoidal"][method], "rows": rows,
+                     "paper_a100_context": {"T": paper[0], "newton_ms": paper[1] * 1e3,
+                                            "sequential_ms": paper[2] * 1e3}}
+    return out
+
+
+def leg_robertson_batch(P, torch, dev, stream, reps=3):
+    """1024 Robertson instances (rates scattered around the paper's, T ~
+    U{1000..5000}), backward Euler, dt = 0.1, plain Newton at tol 1e-10,
+    replayed from a HIP graph; against the sequential GPU integrator of the
+    same rule (one thread per instance)."""
+    import workloads as W
+    w = W.robertson_batch()
+    x0 = torch.tensor(w.x0, device=dev)
+    prm = torch.tensor(w.params, device=dev)
+    lengths = torch.tensor(w.T)
+    total = int(w.T.sum())
+    g = P.SolveGraph(P.ROBERTSON, x0, prm, w.dt, lengths, tol=1e-10, method=P.BACKWARD_EULER,
+                     order="longest_first")
+    ms = _time(lambda: g.launch(stream), reps, stream)
+    ms_seq = _time(lambda: P.seq_integrate(P.ROBERTSON, x0, prm, w.dt, lengths,
+                                           method=P.BACKWARD_EULER, stream=stream), reps, stream)
+    out = {"instances": w.B, "sum_T": total, "ms": ms, "value": total / (ms / 1e3),
+           "launch": "hip graph", "all_ok": bool((g.status == 0).all()),
+           "max_resid": float(g.resid.max()), "updates_mean": float(g.iters.double().mean()),
+           "updates_max": int(g.iters.max()), "sequential_ms": ms_seq,
+           "speedup_of_newton": ms_seq / ms}
+    g.close()
+    return out
+
+
 def leg_adjoint(P, torch, dev, stream, B=256, T=16384, window=0, seg=2048, reps=2):
     """Adjoint on Lorenz-96 (d=40, T=16384, 256 instances): forward windowed
     Newton solve (window 0: picked by the autotuner among 16, 24, 32, 48), loss
@@ -252,7 +327,7 @@ def main():
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and comparator legs")
-    ap.add_argument("--legs", default="scan,dense,vdp,adjoint,kuramoto",
+    ap.add_argument("--legs", default="scan,dense,vdp,adjoint,kuramoto,paper,implicit",
                     help="extra workloads to measure (comma list, or 'none')")
     args = ap.parse_args()
 
@@ -395,6 +470,10 @@ def main():
             extra["adjoint_lorenz96"] = leg_adjoint(P, torch, dev, stream)
         elif leg == "kuramoto":
             extra["kuramoto"] = leg_kuramoto(P, torch, dev, stream)
+        elif leg == "paper":
+            extra["paper_runtime"] = leg_paper_runtime(P, torch, dev, stream)
+        elif leg == "implicit":
+            extra["robertson_batch"] = leg_robertson_batch(P, torch, dev, stream)
         print(f"[bench] leg {leg} done", file=sys.stderr, flush=True)
 
     flops = lorenz96_step_flops(d, args.window)

@@ -219,60 +219,110 @@ __global__ __launch_bounds__(NT) void k_newton_small(SmallKArgs a) {
 
 // ------------------------------------------------ cooperative variant --
 
-// Per-instance control block of the cooperative small-d solver (64 bytes).
+// Cross-workgroup data of the cooperative solver moves with device-scope
+// atomic stores and loads, which are coherent across the chip's L2 slices
+// by themselves: a writer waits for its stores to complete (vmcnt) before
+// it raises a counter or flag, a reader loads only after it has seen it.
+// No device-wide cache writeback or invalidate is needed, because no
+// workgroup reads trajectory states that another workgroup wrote.
+template <typename T>
+__device__ __forceinline__ void co_store(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T co_load(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-instance control block (64 bytes) and the counters of its barrier
+// groups (16 workgroups each, one 64-byte line per counter).
 struct SmallCtl {
-  uint32_t bar_count, bar_gen, err, pad[13];
+  uint32_t gen, top, err, pad[13];
 };
 static_assert(sizeof(SmallCtl) == 64, "control block size");
+constexpr int COOP_GROUP = 16;
+constexpr int LINE_U32 = 16;
 
-// Barrier among the G workgroups of one instance: release fence before
-// arriving, acquire fence after leaving; the wait is bounded (the error word
-// is raised and the wave goes on).
-__device__ __forceinline__ void small_barrier(SmallCtl* c, int G, uint32_t& gen) {
+// Two-level barrier among the G workgroups of one instance: a workgroup
+// arrives on its group's counter; the last of a group arrives on the top
+// counter; the last of those resets the counters and raises the generation
+// that everyone waits for.  Every wait is bounded (the error word is raised
+// and the wave goes on).
+__device__ __forceinline__ void coop_sync(SmallCtl* c, uint32_t* grp, int G, int g, uint32_t& gen) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's posts are complete
     const uint32_t target = gen + 1;
-    const uint32_t prev = atomicAdd(&c->bar_count, 1u);
-    if (prev == (uint32_t)(G - 1)) {
-      __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-      __hip_atomic_store(&c->bar_gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      for (uint64_t it = 0;
-           __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target; it++) {
+    const int gi = g / COOP_GROUP;
+    const int gsize = (G - gi * COOP_GROUP) < COOP_GROUP ? (G - gi * COOP_GROUP) : COOP_GROUP;
+    const int ngrp = (G + COOP_GROUP - 1) / COOP_GROUP;
+    bool released = false;
+    const uint32_t prev = atomicAdd(&grp[gi * LINE_U32], 1u);
+    if (prev == (uint32_t)(gsize - 1)) {
+      co_store(&grp[gi * LINE_U32], 0u);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      const uint32_t p2 = atomicAdd(&c->top, 1u);
+      if (p2 == (uint32_t)(ngrp - 1)) {
+        co_store(&c->top, 0u);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        co_store(&c->gen, target);
+        released = true;
+      }
+    }
+    if (!released)
+      for (uint64_t it = 0; co_load(&c->gen) != target; it++) {
         if (it > (1ull << 28)) {
           atomicOr(&c->err, 1u);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
       }
-    }
-    __threadfence();
     gen = target;
   }
   __syncthreads();
 }
 
+// Workspace of the cooperative solver, per instance (offsets in bytes from
+// the instance's base; see small_coop_stride on the host).
+struct CoopLayout {
+  int G, ngrp;
+  size_t grp_off, agg_off, r_off, bnd_off, flag_off, stride;
+};
+
+__host__ __device__ inline CoopLayout coop_layout(int G, int D, int elem_bytes) {
+  CoopLayout l{};
+  const size_t E = (size_t)D * D + D;
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  l.G = G;
+  l.ngrp = (G + COOP_GROUP - 1) / COOP_GROUP;
+  l.grp_off = up(sizeof(SmallCtl));
+  l.agg_off = l.grp_off + up((size_t)l.ngrp * LINE_U32 * 4);
+  l.r_off = l.agg_off + up(2 * (size_t)G * E * elem_bytes);
+  l.bnd_off = l.r_off + up(2 * (size_t)G * 8);
+  l.flag_off = l.bnd_off + up(2 * (size_t)G * D * elem_bytes);
+  l.stride = l.flag_off + up((size_t)G * LINE_U32 * 4);
+  return l;
+}
+
 // The paper's plain Newton method (Sec. 3.2 / 3.4) for a few long
 // instances, each spread over G co-resident workgroups (cooperative
 // launch); workgroup g owns the contiguous steps [1 + gL, min(T, (g+1)L)],
-// L = ceil(T / G).  Per iteration:
-//   A. each workgroup evaluates the elements of its steps in registers
-//      (the Jacobians are never stored), their residual maximum and the
-//      composition of its elements, and posts both to its slot;
-//   B. after a barrier every workgroup reads all slots: the global residual
-//      gives the stop decision (the same in every workgroup), the
-//      compositions of the workgroups before it, scanned in LDS, give its
-//      carry-in dx at the start of its range;
-//   C. it re-evaluates its elements, scans them chunk by chunk from the
-//      carry-in and writes x += dx in place (the state before its range is
-//      kept from phase A, so every element sees the old iterate);
-// then a barrier before the next iteration.  Results, iteration counts and
-// status follow k_newton_small's plain mode.
+// L = ceil(T / G).  Per iteration k:
+//   A. with x_{lo-1} (x0, or the state workgroup g-1 published at the end
+//      of iteration k-1), each workgroup evaluates the elements of its
+//      steps in registers (the Jacobians are never stored), their residual
+//      maximum and the composition of its elements, and posts both;
+//   B. after one barrier every workgroup reads all posts: the global
+//      residual gives the stop decision (the same everywhere), the
+//      compositions of the workgroups before it, scanned in LDS, give dx at
+//      the start of its range;
+//   C. it re-evaluates its elements, scans them chunk by chunk from that dx,
+//      writes x += dx in place and publishes its new last state for
+//      workgroup g+1.
+// Posts are double-buffered by the parity of k.  Results, iteration counts
+// and status follow k_newton_small's plain mode.
 template <typename T, class S, int M, int NT>
-__global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, SmallCtl* ctl,
-                                                          T* slot_agg, double* slot_r) {
+__global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, char* ws) {
   constexpr int D = S::D, NP = S::NP, E = D * D + D;
   __shared__ Aff<T, D> s_aff[NT / PINT_WAVE];
   __shared__ double s_red[NT / PINT_WAVE];
@@ -281,43 +331,59 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, S
   const int tid = threadIdx.x;
   const int64_t inst = blockIdx.x / G;
   const int g = (int)(blockIdx.x % G);
-  SmallCtl* c = ctl + inst;
-  T* my_agg = slot_agg + (inst * G) * E;
-  double* my_r = slot_r + inst * G;
+  const CoopLayout lay = coop_layout(G, D, (int)sizeof(T));
+  char* base = ws + inst * lay.stride;
+  SmallCtl* c = reinterpret_cast<SmallCtl*>(base);
+  uint32_t* grp = reinterpret_cast<uint32_t*>(base + lay.grp_off);
+  T* post_agg = reinterpret_cast<T*>(base + lay.agg_off);      // [2][G][E]
+  double* post_r = reinterpret_cast<double*>(base + lay.r_off);  // [2][G]
+  T* bnd = reinterpret_cast<T*>(base + lay.bnd_off);            // [2][G][D]
+  uint32_t* bflag = reinterpret_cast<uint32_t*>(base + lay.flag_off);  // [G] (one line each)
   const T dt = (T)a.dt;
   const int64_t Tn = a.T_uniform;
   T* X = static_cast<T*>(a.traj) + inst * Tn * D;
+  const T* xg = static_cast<const T*>(a.x0) + inst * D;
   T P[NP], x0[D];
   {
     const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
 #pragma unroll
     for (int i = 0; i < NP; i++) P[i] = Pg[i];
-    const T* xg = static_cast<const T*>(a.x0) + inst * D;
 #pragma unroll
     for (int i = 0; i < D; i++) x0[i] = xg[i];
   }
   const int64_t L = (Tn + G - 1) / G;
   const int64_t lo = 1 + (int64_t)g * L;
   const int64_t hi = (int64_t)(g + 1) * L < Tn ? (int64_t)(g + 1) * L : Tn;  // empty when lo > hi
-  uint32_t gen = 0;
   if (a.guess == 0)
     for (int64_t n = lo + tid; n <= hi; n += NT)
 #pragma unroll
       for (int i = 0; i < D; i++) X[(n - 1) * D + i] = x0[i];
-  small_barrier(c, G, gen);  // the initial iterate is written everywhere
-
+  // x_{lo-1} of the first iteration: x0, or the caller's initial iterate
+  // (read before any workgroup can have updated it: workgroup g-1 writes
+  // only after the first barrier, which waits for this workgroup)
+  if (tid < D) {
+    const int64_t jb = (lo >= 2 && lo <= hi) ? lo - 2 : 0;  // clamped into the trajectory
+    const T xv = X[jb * D + tid];
+    s_xb[tid] = (lo == 1 || lo > hi || a.guess == 0) ? xg[tid] : xv;
+  }
+  uint32_t gen = 0;
   int64_t k = 0;
   int st = ST_OK;
   double rg = 0.0;
   for (;;) {
+    const int par = (int)(k & 1);
     // ---- A: residual maximum and composition of this workgroup's elements
-    if (tid < D) {
-      // x_{lo-1}: x0, or the last state of the range before (index clamped
-      // into the trajectory, so no load is ever formed outside it)
-      const int64_t jb = (lo >= 2 && lo <= hi) ? lo - 2 : 0;
-      const T xv = X[jb * D + tid];
-      const T* xg = static_cast<const T*>(a.x0) + inst * D;
-      s_xb[tid] = (lo == 1 || lo > hi) ? xg[tid] : xv;
+    if (k > 0 && g > 0 && lo <= hi) {
+      if (tid == 0)  // the state workgroup g-1 published at the end of iteration k-1
+        for (uint64_t it = 0; co_load(&bflag[(g - 1) * LINE_U32]) < (uint32_t)k; it++) {
+          if (it > (1ull << 28)) {
+            atomicOr(&c->err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      __syncthreads();
+      if (tid < D) s_xb[tid] = co_load(&bnd[((1 - par) * G + (g - 1)) * D + tid]);
     }
     if (tid == 0) aff_identity(s_run);
     __syncthreads();
@@ -348,30 +414,31 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, S
       __syncthreads();
     }
     r = block_max<NT>(r, s_red);
-    if (tid < D * D) my_agg[g * E + tid] = s_run.A[tid];
-    if (tid < D) my_agg[g * E + D * D + tid] = s_run.b[tid];
-    if (tid == 0) my_r[g] = r;
-    small_barrier(c, G, gen);
+    if (tid < D * D) co_store(&post_agg[(par * G + g) * E + tid], s_run.A[tid]);
+    if (tid < D) co_store(&post_agg[(par * G + g) * E + D * D + tid], s_run.b[tid]);
+    if (tid == 0) co_store(&post_r[par * G + g], r);
+    coop_sync(c, grp, G, g, gen);
 
-    // ---- B: global residual and stop test; carry-in from the earlier ranges
+    // ---- B: global residual and stop test; dx at the start of this range
     double rr = 0.0;
-    for (int j = tid; j < G; j += NT) rr = fmax(rr, my_r[j]);
+    for (int j = tid; j < G; j += NT) rr = fmax(rr, co_load(&post_r[par * G + j]));
     rg = block_max<NT>(rr, s_red);
     if (!(rg < INFINITY)) { st = ST_NONFINITE; break; }
     if (rg < a.tol) { st = ST_OK; break; }
     if (k >= a.max_iter) { st = ST_NOT_CONVERGED; break; }
     {
-      // aggregates 0..g-1 in order: thread t folds a contiguous run of them,
-      // then a block scan; the composed map applied to dx = 0 is its b-part
+      // compositions 0..g-1 in order: thread t folds a contiguous run of
+      // them, then a block scan; the whole map applied to dx = 0 is its b-part
       const int q = (g + NT - 1) / NT;
       Aff<T, D> e;
       aff_identity(e);
       for (int j = tid * q; j < (tid + 1) * q && j < g; j++) {
         Aff<T, D> f;
+        const T* pj = post_agg + (par * G + j) * E;
 #pragma unroll
-        for (int i = 0; i < D * D; i++) f.A[i] = my_agg[j * E + i];
+        for (int i = 0; i < D * D; i++) f.A[i] = co_load(&pj[i]);
 #pragma unroll
-        for (int i = 0; i < D; i++) f.b[i] = my_agg[j * E + D * D + i];
+        for (int i = 0; i < D; i++) f.b[i] = co_load(&pj[D * D + i]);
         aff_after(f, e);
         e = f;
       }
@@ -422,11 +489,16 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, S
 #pragma unroll
         for (int i = 0; i < D; i++) X[(n - 1) * D + i] = xc[i] + dx[i];
       }
+      if (n == hi && g + 1 < G) {  // publish the new last state for workgroup g+1
+#pragma unroll
+        for (int i = 0; i < D; i++) co_store(&bnd[(par * G + g) * D + i], xc[i] + dx[i]);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        co_store(&bflag[g * LINE_U32], (uint32_t)(k + 1));
+      }
       __syncthreads();
       if (tid < D) { s_xprev[tid] = s_xlast[tid]; s_z[tid] = s_zlast[tid]; }
       __syncthreads();
     }
-    small_barrier(c, G, gen);
     k++;
   }
   if (g == 0 && tid == 0) {
@@ -555,10 +627,10 @@ struct SmallLaunch {
   int op, dtype, system, d;
   int grid, block;
   hipStream_t stream;
-  void* out0;      // residual: h; elements: A; coop: slot aggregates
-  void* out1;      // elements: b; coop: slot residuals (double)
+  void* out0;      // residual: h; elements: A
+  void* out1;      // elements: b
   double* hmax;    // residual
-  SmallCtl* ctl;   // coop: control blocks
+  char* coop_ws;   // coop: per-instance control blocks and posts (coop_layout)
   int G;           // coop: workgroups per instance
   int* occupancy;  // coop occupancy query: resident workgroups per CU
 };
@@ -595,10 +667,8 @@ int small_launch(const SmallKArgs& k, const SmallLaunch& l) {
       case OP_COOP: {
         SmallKArgs kk = k;
         int G = l.G;
-        SmallCtl* ctl = l.ctl;
-        T* agg = static_cast<T*>(l.out0);
-        double* rs = static_cast<double*>(l.out1);
-        void* args[] = {&kk, &G, &ctl, &agg, &rs};
+        char* cw = l.coop_ws;
+        void* args[] = {&kk, &G, &cw};
         return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_newton_small_coop<T, S, M, NT_COOP>),
                                           dim3(l.grid), dim3(NT_COOP), args, 0, l.stream) == hipSuccess
                    ? ST_OK : ST_DEVICE;

@@ -65,15 +65,14 @@ static int num_cus_small() {
 }
 
 // Workgroups per instance of the cooperative solver, or 0 when the batched
-// one-workgroup-per-instance solver is used instead: plain mode, a horizon
-// of at least four chunks per workgroup for four or more workgroups, and
-// all B * G workgroups resident at once.
+// one-workgroup-per-instance solver is used instead: plain mode, `tile`
+// steps per workgroup (rounded up to whole chunks of NT_COOP; 0 means one
+// chunk), at least four workgroups, all B * G of them resident at once.
 static int coop_groups_small(const SolveArgs& a) {
   if (a.window > 0 || a.B <= 0) return 0;
   const int64_t T = a.T_off ? a.T_max : a.T_uniform;
-  const int64_t per = 4 * (int64_t)NT_COOP;
+  const int64_t per = a.tile > 0 ? ((int64_t)a.tile + NT_COOP - 1) / NT_COOP * NT_COOP : NT_COOP;
   int64_t G = (T + per - 1) / per;
-  if (G > 1024) G = 1024;
   int per_cu = 0;
   SmallLaunch l{};
   l.op = OP_COOP_OCCUPANCY;
@@ -81,43 +80,33 @@ static int coop_groups_small(const SolveArgs& a) {
   if (run(a, SmallKArgs{}, l) != ST_OK || per_cu <= 0) return 0;
   const int64_t cap = (int64_t)per_cu * num_cus_small();
   if (a.B * G > cap) G = cap / a.B;
+  if (G < 4) return 0;
+  G = (T + (T + G - 1) / G - 1) / ((T + G - 1) / G);  // no empty range at the end
   return G >= 4 ? (int)G : 0;
 }
 
-struct SmallWs {
-  size_t ctl_off, agg_off, r_off, total;
-};
-
-static SmallWs small_ws_layout(const SolveArgs& a, int G) {
-  SmallWs l{};
-  const size_t sz = a.dtype == 0 ? 8 : 4;
-  const size_t E = (size_t)a.d * a.d + a.d;
-  const size_t nslot = G > 0 ? (size_t)a.B * G : 0;
-  l.ctl_off = 256;
-  l.agg_off = l.ctl_off + align_up((G > 0 ? (size_t)a.B : 0) * sizeof(SmallCtl));
-  l.r_off = l.agg_off + align_up(nslot * E * sz);
-  l.total = l.r_off + align_up(nslot * sizeof(double));
-  return l;
+static size_t coop_bytes(const SolveArgs& a, int G) {
+  if (G <= 0) return 0;
+  return coop_layout(G, a.d, a.dtype == 0 ? 8 : 4).stride * (size_t)a.B;
 }
 
-size_t small_ws_bytes(const SolveArgs& a) { return small_ws_layout(a, coop_groups_small(a)).total; }
+size_t small_ws_bytes(const SolveArgs& a) { return 256 + coop_bytes(a, coop_groups_small(a)); }
 
 int small_solve(const SolveArgs& a) {
   const int G = a.T_off ? 0 : coop_groups_small(a);
-  const SmallWs wl = small_ws_layout(a, G);
-  if (a.ws_bytes < wl.total || a.ws == nullptr) return ST_WORKSPACE;
+  const size_t need = 256 + coop_bytes(a, G);
+  if (a.ws_bytes < need || a.ws == nullptr) return ST_WORKSPACE;
   SmallKArgs k = to_k(a);
   char* w = static_cast<char*>(a.ws);
   if (G > 0) {
-    // control blocks start at zero (a kernel, not a memset)
-    if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w), wl.agg_off / 4, 0u, a.stream)) return rc;
+    // control blocks, counters and flags start at zero (a kernel, not a memset)
+    if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w + 256), coop_bytes(a, G) / 4, 0u, a.stream))
+      return rc;
     SmallLaunch l{};
     l.op = OP_COOP;
     l.grid = (int)(a.B * G);
     l.G = G;
-    l.ctl = reinterpret_cast<SmallCtl*>(w + wl.ctl_off);
-    l.out0 = w + wl.agg_off;
-    l.out1 = w + wl.r_off;
+    l.coop_ws = w + 256;
     if (run(a, k, l) == ST_OK) return ST_OK;
     (void)hipGetLastError();  // not launchable cooperatively: the batched solver below
   }

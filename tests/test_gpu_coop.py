@@ -109,3 +109,23 @@ def test_fp32_long_logistic(pint, orc):
     assert np.abs(got[:1000] - ref[:1000]).max() <= 1e-4 * scale
     print(f"fp32 logistic T={T}: K={int(iters) + 1}, max rel err over all steps "
           f"{np.abs(got - ref).max() / scale:.2e}")
+
+
+@pytest.mark.parametrize("tile", [0, 1024, 4096])
+def test_robertson_longest_horizon_any_range_size(pint, orc, tile):
+    """The paper's longest implicit run (Robertson, dt = 5e-3, T = 1e5,
+    Figures 7 and 9): K = 24 and the oracle's iterate, whatever the number
+    of steps per workgroup (the tile option)."""
+    pin = next(p for p in W.implicit_pins() if p["name"] == "robertson")
+    T = 100000
+    z = np.zeros((T, 3))
+    ref = orc.newton_implicit(orc.BEULER, pin["system"], pin["params"], 5e-3, T, pin["x0"],
+                              guess=z, tol=PAPER_TOL, max_iter=60)
+    print(f"[robertson] T={T} tile={tile}", flush=True)
+    traj, iters, resid, status = pint.solve(pint.ROBERTSON, _t(pin["x0"]), _t(pin["params"]), 5e-3,
+                                            T, tol=PAPER_TOL, max_iter=60, guess=_t(z), tile=tile,
+                                            method=pint.BACKWARD_EULER)
+    torch.cuda.synchronize()
+    assert int(status) == pint.OK == ref["status"]
+    assert int(iters) + 1 == ref["iters"] + 1 == 24
+    assert np.abs(traj.cpu().numpy() - ref["traj"]).max() <= 1e-10
