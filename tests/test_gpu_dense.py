@@ -71,8 +71,12 @@ def test_residual_and_elements(pint, orc, kind):
             assert np.abs(A[b, n] - J).max() <= 1e-12 * max(1.0, np.abs(J).max()), (b, n)
 
 
-@pytest.mark.parametrize("T,window,tol", [(96, 32, 1e-12), (128, 200, 1e-12), (64, 0, 1e-12)])
+@pytest.mark.parametrize("T,window,tol", [(96, 32, 1e-12), (128, 200, 1e-12), (64, 0, 1e-12),
+                                          (256, 20, 1e-12), (256, 64, 1e-12), (256, 108, 1e-12),
+                                          (300, 120, 1e-12)])
 def test_lorenz96_same_iterate_short(pint, orc, T, window, tol):
+    """Same iterate and iteration count as the oracle, for windows from 20 to
+    200 steps (the fold walks them in chunks of 12 staged steps)."""
     w = W.lorenz96(T=T)
     print(f"[l96] T={T} W={window} tol={tol}", flush=True)
     ref = orc.newton(w.system, w.params[0], w.dt, T, w.x0[0], tol=tol, window=window,
