@@ -324,10 +324,16 @@ __host__ __device__ inline CoopLayout coop_layout(int G, int D, int elem_bytes) 
 template <typename T, class S, int M, int NT>
 __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, char* ws) {
   constexpr int D = S::D, NP = S::NP, E = D * D + D;
+  // Ranges of at most KC chunks keep phase A's scanned elements and old
+  // states in registers, so phase C only applies them to the carry-in (x is
+  // read once and written once per iteration); longer ranges re-evaluate.
+  constexpr int KC = D <= 2 ? 2 : (D == 3 ? 1 : 0);
+  constexpr int KR = KC > 0 ? KC : 1;
   __shared__ Aff<T, D> s_aff[NT / PINT_WAVE];
   __shared__ double s_red[NT / PINT_WAVE];
   __shared__ T s_z[D], s_xprev[D], s_xlast[D], s_zlast[D], s_xb[D];
   __shared__ Aff<T, D> s_run;
+  __shared__ Aff<T, D> s_cagg[KR];
   const int tid = threadIdx.x;
   const int64_t inst = blockIdx.x / G;
   const int g = (int)(blockIdx.x % G);
@@ -354,6 +360,10 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, c
   const int64_t L = (Tn + G - 1) / G;
   const int64_t lo = 1 + (int64_t)g * L;
   const int64_t hi = (int64_t)(g + 1) * L < Tn ? (int64_t)(g + 1) * L : Tn;  // empty when lo > hi
+  const int nch = lo <= hi ? (int)((hi - lo) / NT + 1) : 0;
+  const bool fast = nch <= KC;
+  Aff<T, D> eS[KR];
+  T xS[KR][D];
   if (a.guess == 0)
     for (int64_t n = lo + tid; n <= hi; n += NT)
 #pragma unroll
@@ -388,11 +398,12 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, c
     if (tid == 0) aff_identity(s_run);
     __syncthreads();
     double r = 0.0;
-    for (int64_t c0 = lo; c0 <= hi; c0 += NT) {
+    // one chunk of phase A: element of step n (identity past the range),
+    // residual, in-chunk inclusive scan, composition into the range's map
+    auto chunk_a = [&](int64_t c0, Aff<T, D>& e, T (&xc)[D]) {
       const int64_t n = c0 + tid;
-      Aff<T, D> e;
       if (n <= hi) {
-        T xp[D], xc[D];
+        T xp[D];
         const T* xq = X + (n >= 2 ? n - 2 : 0) * D;  // x_{n-1} when n > lo
 #pragma unroll
         for (int i = 0; i < D; i++) {
@@ -404,14 +415,31 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, c
         for (int i = 0; i < D; i++) r = acc_norm(r, e.b[i]);  // |b_n| is the tested residual
       } else {
         aff_identity(e);
+#pragma unroll
+        for (int i = 0; i < D; i++) xc[i] = T(0);
       }
       block_scan_aff<T, D, NT>(e, s_aff);
       if (tid == NT - 1) {
         Aff<T, D> run = s_run;
-        aff_after(e, run);  // this chunk after everything before it
-        s_run = e;
+        Aff<T, D> ch = e;
+        aff_after(ch, run);  // this chunk after everything before it
+        s_run = ch;
       }
       __syncthreads();
+    };
+    if (fast) {
+#pragma unroll
+      for (int ci = 0; ci < KC; ci++)
+        if (ci < nch) {
+          chunk_a(lo + (int64_t)ci * NT, eS[ci], xS[ci]);
+          if (tid == NT - 1) s_cagg[ci] = eS[ci];
+        }
+    } else {
+      for (int64_t c0 = lo; c0 <= hi; c0 += NT) {
+        Aff<T, D> e;
+        T xc[D];
+        chunk_a(c0, e, xc);
+      }
     }
     r = block_max<NT>(r, s_red);
     if (tid < D * D) co_store(&post_agg[(par * G + g) * E + tid], s_run.A[tid]);
@@ -452,7 +480,48 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, c
     }
 
     // ---- C: the update over this workgroup's range
-    for (int64_t c0 = lo; c0 <= hi; c0 += NT) {
+    if (fast) {
+      // dx_n = (in-chunk prefix of step n) applied to dx at the chunk's
+      // start; that dx goes from chunk to chunk through the chunk maps
+      T z[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) z[i] = s_z[i];
+#pragma unroll
+      for (int ci = 0; ci < KC; ci++)
+        if (ci < nch) {
+          const int64_t n = lo + (int64_t)ci * NT + tid;
+          if (n <= hi) {
+            T xn[D];
+#pragma unroll
+            for (int i = 0; i < D; i++) {
+              T acc = eS[ci].b[i];
+#pragma unroll
+              for (int j = 0; j < D; j++) acc += eS[ci].A[i * D + j] * z[j];
+              xn[i] = xS[ci][i] + acc;
+              X[(n - 1) * D + i] = xn[i];
+            }
+            if (n == hi && g + 1 < G) {  // publish the new last state for workgroup g+1
+#pragma unroll
+              for (int i = 0; i < D; i++) co_store(&bnd[(par * G + g) * D + i], xn[i]);
+              asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+              co_store(&bflag[g * LINE_U32], (uint32_t)(k + 1));
+            }
+          }
+          const Aff<T, D> cg = s_cagg[ci];
+          T zn[D];
+#pragma unroll
+          for (int i = 0; i < D; i++) {
+            T acc = cg.b[i];
+#pragma unroll
+            for (int j = 0; j < D; j++) acc += cg.A[i * D + j] * z[j];
+            zn[i] = acc;
+          }
+#pragma unroll
+          for (int i = 0; i < D; i++) z[i] = zn[i];
+        }
+      __syncthreads();
+    }
+    for (int64_t c0 = lo; c0 <= hi && !fast; c0 += NT) {
       const int64_t n = c0 + tid;
       const bool act = n <= hi;
       T xc[D];
