@@ -110,7 +110,9 @@ typedef struct {
   double tol;        /* stop when ||h(xi)||_inf < tol (strict)                   */
   double guard;      /* windowed mode: an updated state with |x| > guard (or     */
                      /* non-finite) ends the accepted part of the update         */
-  int32_t tile;      /* scan tile / chunk hint; 0 = library default              */
+  int32_t tile;      /* scan tile / chunk hint; 0 = library default.  For the   */
+                     /* cooperative small-d solve (below): steps per workgroup, */
+                     /* rounded up to whole chunks of 256; 0 = one chunk        */
   int32_t flags;     /* reserved, must be 0                                      */
   /* Launch shape of the batched small-d solver (d <= 4); results do not
    * depend on them.  Dense dimensions require 0 / 0 / NULL. */
@@ -173,7 +175,14 @@ pint_status pint_solve_varlen(const pint_system* sys, int64_t B, const void* x0,
 /* pint_solve — as pint_solve_varlen with every instance of length T
  * (traj is [B][T][d]).  An instance of dense dimension runs on several
  * workgroups at once (cooperative launch with device-side barriers between
- * them); like every entry point, the call only enqueues work. */
+ * them).  So does a small-d instance in plain mode (window 0) when the
+ * horizon spans at least four chunks of 256 steps and the B * G workgroups
+ * fit on the device at once: each workgroup owns a contiguous range of
+ * steps, evaluates its elements in registers and exchanges only range
+ * compositions and boundary states with the others, one grid barrier per
+ * Newton iteration (the workspace from pint_workspace_bytes covers it).
+ * Results follow the same plain-mode rules.  Like every entry point, the
+ * call only enqueues work. */
 pint_status pint_solve(const pint_system* sys, int64_t B, const void* x0,
                        double dt, int64_t T, const pint_options* opts,
                        void* traj, int64_t* iters, double* resid,
