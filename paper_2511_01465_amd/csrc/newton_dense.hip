@@ -346,6 +346,52 @@ __device__ __forceinline__ void lds_copy(T* dst, const T* __restrict__ src, int 
   }
 }
 
+// Three lds_copy's at once: every global load of the three arrays is issued
+// before the first LDS store, so staging costs one memory latency, not
+// three.  16-byte vectors when every pointer is aligned and every length is
+// a whole number of vectors; otherwise the three copies one after another.
+template <typename T, int MV1, int MV2>
+__device__ __forceinline__ void lds_copy3(T* d1, const T* __restrict__ s1, int n1, T* d2,
+                                          const T* __restrict__ s2, int n2, T* d3,
+                                          const T* __restrict__ s3, int n3, int t, int nt) {
+  constexpr int V = 16 / sizeof(T);
+  typedef T v_t __attribute__((ext_vector_type(V)));
+  auto al = [](const void* q) { return reinterpret_cast<uintptr_t>(q) % 16 == 0; };
+  if (!(al(d1) && al(s1) && al(d2) && al(s2) && al(d3) && al(s3) && n1 % V == 0 && n2 % V == 0 &&
+        n3 % V == 0)) {
+    lds_copy<T, MV1>(d1, s1, n1, t, nt);
+    lds_copy<T, MV2>(d2, s2, n2, t, nt);
+    lds_copy<T, MV2>(d3, s3, n3, t, nt);
+    return;
+  }
+  const int nv1 = n1 / V, nv2 = n2 / V, nv3 = n3 / V;
+  for (int v1 = 0, v2 = 0; v1 < nv1 || v2 < nv2 || v2 < nv3; v1 += MV1 * nt, v2 += MV2 * nt) {
+    v_t r1[MV1], r2[MV2], r3[MV2];
+#pragma unroll
+    for (int u = 0; u < MV1; u++) {
+      const int v = v1 + u * nt + t;
+      if (v < nv1) r1[u] = reinterpret_cast<const v_t*>(s1)[v];
+    }
+#pragma unroll
+    for (int u = 0; u < MV2; u++) {
+      const int v = v2 + u * nt + t;
+      if (v < nv2) r2[u] = reinterpret_cast<const v_t*>(s2)[v];
+      if (v < nv3) r3[u] = reinterpret_cast<const v_t*>(s3)[v];
+    }
+#pragma unroll
+    for (int u = 0; u < MV1; u++) {
+      const int v = v1 + u * nt + t;
+      if (v < nv1) reinterpret_cast<v_t*>(d1)[v] = r1[u];
+    }
+#pragma unroll
+    for (int u = 0; u < MV2; u++) {
+      const int v = v2 + u * nt + t;
+      if (v < nv2) reinterpret_cast<v_t*>(d2)[v] = r2[u];
+      if (v < nv3) reinterpret_cast<v_t*>(d3)[v] = r3[u];
+    }
+  }
+}
+
 template <typename T, class S>
 __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, const T* Bd, const T* bb,
                                                 const T* Xw, T* xnb, int64_t len, bool plain, double guard) {
@@ -360,9 +406,8 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
   constexpr int MVB = (CH * NB / V + NL - 1) / NL, MVX = (CH * D / V + NL - 1) / NL;
   auto load = [&](int64_t c0, int n, int h) {
     T* dst = lbuf + (size_t)h * CH * PER;
-    lds_copy<T, MVB>(dst, Bd + c0 * NB, n * NB, lt, nl);
-    lds_copy<T, MVX>(dst + CH * NB, bb + c0 * D, n * D, lt, nl);
-    lds_copy<T, MVX>(dst + CH * NB + CH * D, Xw + c0 * D, n * D, lt, nl);
+    lds_copy3<T, MVB, MVX>(dst, Bd + c0 * NB, n * NB, dst + CH * NB, bb + c0 * D, n * D,
+                           dst + CH * NB + CH * D, Xw + c0 * D, n * D, lt, nl);
   };
   const int64_t nch = (len + CH - 1) / CH;
   if (wv > 0 && len > 0) load(0, (int)(len < CH ? len : CH), 0);
@@ -371,60 +416,136 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
   // as zx[p] = dx[(p - BOFF) mod D], p < D + BW - 1, so row i reads the
   // consecutive zx[i .. i+BW-1] (one wave writes and reads: in order).
   static_assert(D + BW - 1 <= 2 * D, "zx fits in sm.z");
-  T* zx = &sm.z[0][0];
-  const int i = lane < D ? lane : 0;
   int64_t bad = INT64_MAX;
-  for (int64_t c = 0; c < nch; c++) {
-    const int64_t c0 = c * CH;
-    const int n = (int)((len - c0) < CH ? (len - c0) : CH);
-    if (wv > 0) {
-      if (c + 1 < nch) {
-        const int64_t c1 = c0 + CH;
-        load(c1, (int)((len - c1) < CH ? (len - c1) : CH), (int)((c + 1) & 1));
-      }
-    } else if (bad == INT64_MAX) {
-      const T* L = lbuf + (size_t)(c & 1) * CH * PER;
-      for (int m = 0; m < n; m++) {
-        const T* band = L + m * NB;
-        T a0 = L[CH * NB + m * D + i], a1 = T(0);
-        if (c0 + m > 0) {
-          // issue all LDS reads of the step, then the multiply-adds
-          T bv[BW], zv[BW];
+  // Lorenz-96's shape (d = 40, 13 diagonals from offset -8): dx stays in
+  // registers.  Lane l < 52 holds dx of row (l - 8) mod d; lanes 8..47 own
+  // rows 0..39, lanes 0..7 and 48..51 are copies.  Row i's neighbours
+  // dx_{i-8} .. dx_{i+4} are then lanes l-8 .. l+4 of the owner lane l, one
+  // chain of whole-wave DPP shifts to each side; after a step the copies are
+  // refreshed from their owners by one lane permutation.
+  constexpr bool REG_FOLD = (D == 40 && BW == 13 && BOFF == 8);
+  if constexpr (REG_FOLD) {
+    constexpr int DPP_WAVE_SHR1 = 0x138;  // lane l <- lane l - 1
+    constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l <- lane l + 1
+    const bool owner = lane >= 8 && lane < 8 + D;
+    const int row = lane < 52 ? (lane + D - 8) % D : 0;
+    const int src = lane < 8 ? lane + D : (lane >= 8 + D && lane < 52 ? lane - D : lane);
+    T zr = T(0);
+    for (int64_t c = 0; c < nch; c++) {
+      const int64_t c0 = c * CH;
+      const int n = (int)((len - c0) < CH ? (len - c0) : CH);
+      if (wv > 0) {
+        if (c + 1 < nch) {
+          const int64_t c1 = c0 + CH;
+          load(c1, (int)((len - c1) < CH ? (len - c1) : CH), (int)((c + 1) & 1));
+        }
+      } else if (bad == INT64_MAX) {
+        const T* L = lbuf + (size_t)(c & 1) * CH * PER;
+        for (int m = 0; m < n; m++) {
+          const T* band = L + m * NB;
+          T bv[BW];
 #pragma unroll
-          for (int k = 0; k < BW; k++) {
-            bv[k] = band[k * D + i];
-            zv[k] = zx[i + k];
-          }
-          __builtin_amdgcn_sched_barrier(0);
+          for (int k = 0; k < BW; k++) bv[k] = band[k * D + row];
+          T a0 = L[CH * NB + m * D + row], a1 = T(0);
+          if (c0 + m > 0) {
+            T nb[BW];
+            nb[BOFF] = zr;
+            T t = zr;
 #pragma unroll
-          for (int k = 0; k < BW; k++) {
-            if (k & 1)
-              a1 += bv[k] * zv[k];
-            else
-              a0 += bv[k] * zv[k];
+            for (int q = 1; q <= BOFF; q++) {
+              t = dpp_row<DPP_WAVE_SHR1, 0xf>(T(0), t);
+              nb[BOFF - q] = t;
+            }
+            t = zr;
+#pragma unroll
+            for (int q = 1; q < BW - BOFF; q++) {
+              t = dpp_row<DPP_WAVE_SHL1, 0xf>(T(0), t);
+              nb[BOFF + q] = t;
+            }
+#pragma unroll
+            for (int k = 0; k < BW; k++) {
+              if (k & 1)
+                a1 += bv[k] * nb[k];
+              else
+                a0 += bv[k] * nb[k];
+            }
           }
+          T z = a0 + a1;
+          // copies take their owner's new value
+          if constexpr (sizeof(T) == 8) {
+            const int lo = __builtin_amdgcn_ds_bpermute(src * 4, __double2loint((double)z));
+            const int hi = __builtin_amdgcn_ds_bpermute(src * 4, __double2hiint((double)z));
+            zr = (T)__hiloint2double(hi, lo);
+          } else {
+            zr = __int_as_float(__builtin_amdgcn_ds_bpermute(src * 4, __float_as_int((float)z)));
+          }
+          const T xn = L[CH * NB + CH * D + m * D + row] + z;
+          if (owner) {
+            xnb[(c0 + m) * D + row] = xn;
+            if (!plain && (!finite_(xn) || fabs((double)xn) > guard)) bad = c0 + m;
+          }
+          // the first cut step ends the fold (later states are not used)
+          if (!plain && __ballot(bad != INT64_MAX)) break;
         }
-        const T z = a0 + a1;
-        if (lane < D) {
-          zx[i + BOFF] = z;
-          if (i >= D - BOFF) zx[i + BOFF - D] = z;
-          if (i + BOFF + D < D + BW - 1) zx[i + BOFF + D] = z;
-        }
-        // other lanes read these next step; within one thread those addresses
-        // need not alias, so keep the compiler from moving reads above them
-        // (the hardware completes one wave's LDS operations in order)
-        asm volatile("" ::: "memory");
-        const T xn = L[CH * NB + CH * D + m * D + i] + z;
-        if (lane < D) {
-          xnb[(c0 + m) * D + i] = xn;
-          if (!plain && (!finite_(xn) || fabs((double)xn) > guard)) bad = c0 + m;
-        }
-        // the first cut step ends the fold (later states are not used)
-        if (!plain && __ballot(bad != INT64_MAX)) break;
+        bad = wave_min_i64(owner ? bad : INT64_MAX);
       }
-      bad = wave_min_i64(lane < D ? bad : INT64_MAX);
+      lds_barrier();  // chunk c+1 staged, chunk c folded
     }
-    lds_barrier();  // chunk c+1 staged, chunk c folded
+  } else {
+    T* zx = &sm.z[0][0];
+    const int i = lane < D ? lane : 0;
+    for (int64_t c = 0; c < nch; c++) {
+      const int64_t c0 = c * CH;
+      const int n = (int)((len - c0) < CH ? (len - c0) : CH);
+      if (wv > 0) {
+        if (c + 1 < nch) {
+          const int64_t c1 = c0 + CH;
+          load(c1, (int)((len - c1) < CH ? (len - c1) : CH), (int)((c + 1) & 1));
+        }
+      } else if (bad == INT64_MAX) {
+        const T* L = lbuf + (size_t)(c & 1) * CH * PER;
+        for (int m = 0; m < n; m++) {
+          const T* band = L + m * NB;
+          T a0 = L[CH * NB + m * D + i], a1 = T(0);
+          if (c0 + m > 0) {
+            // issue all LDS reads of the step, then the multiply-adds
+            T bv[BW], zv[BW];
+  #pragma unroll
+            for (int k = 0; k < BW; k++) {
+              bv[k] = band[k * D + i];
+              zv[k] = zx[i + k];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+  #pragma unroll
+            for (int k = 0; k < BW; k++) {
+              if (k & 1)
+                a1 += bv[k] * zv[k];
+              else
+                a0 += bv[k] * zv[k];
+            }
+          }
+          const T z = a0 + a1;
+          if (lane < D) {
+            zx[i + BOFF] = z;
+            if (i >= D - BOFF) zx[i + BOFF - D] = z;
+            if (i + BOFF + D < D + BW - 1) zx[i + BOFF + D] = z;
+          }
+          // other lanes read these next step; within one thread those addresses
+          // need not alias, so keep the compiler from moving reads above them
+          // (the hardware completes one wave's LDS operations in order)
+          asm volatile("" ::: "memory");
+          const T xn = L[CH * NB + CH * D + m * D + i] + z;
+          if (lane < D) {
+            xnb[(c0 + m) * D + i] = xn;
+            if (!plain && (!finite_(xn) || fabs((double)xn) > guard)) bad = c0 + m;
+          }
+          // the first cut step ends the fold (later states are not used)
+          if (!plain && __ballot(bad != INT64_MAX)) break;
+        }
+        bad = wave_min_i64(lane < D ? bad : INT64_MAX);
+      }
+      lds_barrier();  // chunk c+1 staged, chunk c folded
+    }
   }
   if (tid == 0) sm.redi[0] = bad;
   __syncthreads();  // also: wave 0's updated states are visible to dn_commit
