@@ -247,9 +247,14 @@ __device__ __forceinline__ int64_t dn_fold(DenseSmem<T, S>& sm, const T* AT, con
 #pragma unroll
             for (int jj = 0; jj < JC; jj++) part += ring[u][jj] * sm.z[cur][rq * JC + jj];
           } else {
+            // every load of the step's slice in flight at once (one memory
+            // latency per step), then the multiply-adds
             const T* Am = AT + m * D * D;
-#pragma unroll 16
-            for (int jj = 0; jj < JC; jj++) part += Am[(int64_t)(rq * JC + jj) * D + ri] * sm.z[cur][rq * JC + jj];
+            T av[JC];
+#pragma unroll
+            for (int jj = 0; jj < JC; jj++) av[jj] = Am[(int64_t)(rq * JC + jj) * D + ri];
+#pragma unroll
+            for (int jj = 0; jj < JC; jj++) part += av[jj] * sm.z[cur][rq * JC + jj];
           }
         }
         T bm = T(0), xm = T(0);
