@@ -485,12 +485,10 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
             zr = __int_as_float(__builtin_amdgcn_ds_bpermute(src * 4, __float_as_int((float)z)));
           }
           const T xn = L[CH * NB + CH * D + m * D + row] + z;
-          if (owner) {
-            xnb[(c0 + m) * D + row] = xn;
-            if (!plain && (!finite_(xn) || fabs((double)xn) > guard)) bad = c0 + m;
-          }
-          // the first cut step ends the fold (later states are not used)
+          if (owner && !plain && (!finite_(xn) || fabs((double)xn) > guard)) bad = c0 + m;
+          // the first cut step ends the fold; it and later steps stay unwritten
           if (!plain && __ballot(bad != INT64_MAX)) break;
+          if (owner) xnb[(c0 + m) * D + row] = xn;
         }
         bad = wave_min_i64(owner ? bad : INT64_MAX);
       }
@@ -540,12 +538,10 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
           // (the hardware completes one wave's LDS operations in order)
           asm volatile("" ::: "memory");
           const T xn = L[CH * NB + CH * D + m * D + i] + z;
-          if (lane < D) {
-            xnb[(c0 + m) * D + i] = xn;
-            if (!plain && (!finite_(xn) || fabs((double)xn) > guard)) bad = c0 + m;
-          }
-          // the first cut step ends the fold (later states are not used)
+          if (lane < D && !plain && (!finite_(xn) || fabs((double)xn) > guard)) bad = c0 + m;
+          // the first cut step ends the fold; it and later steps stay unwritten
           if (!plain && __ballot(bad != INT64_MAX)) break;
+          if (lane < D) xnb[(c0 + m) * D + i] = xn;
         }
         bad = wave_min_i64(lane < D ? bad : INT64_MAX);
       }
@@ -630,10 +626,11 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense(DenseKArgs a) {
       dn_elements<T, S>(sm, dt, X, lo, len, 0, 1, AT, bb);
       int64_t q;
       if constexpr (S::BANDED)
-        q = dn_fold_band<T, S>(sm, band_buf, AT, bb, X + (lo - 1) * D, dxb, len, plain, a.guard);
+        // the accepted states go straight into the trajectory
+        q = dn_fold_band<T, S>(sm, band_buf, AT, bb, X + (lo - 1) * D, X + (lo - 1) * D, len, plain, a.guard);
       else
         q = dn_fold<T, S>(sm, AT, bb, X + (lo - 1) * D, dxb, len, plain, a.guard);
-      dn_commit<T, S>(X + (lo - 1) * D, dxb, q);
+      if constexpr (!S::BANDED) dn_commit<T, S>(X + (lo - 1) * D, dxb, q);
       if (q == 0) { st = ST_NONFINITE; break; }
       k++;
     }
@@ -857,11 +854,12 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
         constexpr int64_t ES = S::BANDED ? (int64_t)S::BW * D : (int64_t)D * D;  // scalars per element
         int64_t q;
         if constexpr (S::BANDED)
-          q = dn_fold_band<T, S>(sm, band_buf, AT + off * ES, bb + off * D, X + (p - 1) * D, dxb, len, false,
-                                 a.guard);
+          // the accepted states go straight into the trajectory
+          q = dn_fold_band<T, S>(sm, band_buf, AT + off * ES, bb + off * D, X + (p - 1) * D, X + (p - 1) * D,
+                                 len, false, a.guard);
         else
           q = dn_fold<T, S>(sm, AT + off * ES, bb + off * D, X + (p - 1) * D, dxb, len, false, a.guard);
-        dn_commit<T, S>(X + (p - 1) * D, dxb, q);
+        if constexpr (!S::BANDED) dn_commit<T, S>(X + (p - 1) * D, dxb, q);
         if (q == 0) {
           st = ST_NONFINITE;
           done = 1;
