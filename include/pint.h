@@ -153,7 +153,9 @@ size_t pint_workspace_bytes(const pint_system* sys, int64_t B, int64_t T_total,
  *                             out: the last iterate (x_1..x_T per instance)
  *   iters   [B] int64         Newton updates applied (the paper's K is iters+1)
  *   resid   [B] double        ||h||_inf of the returned iterate
- *   status  [B] int32         PINT_OK / PINT_NOT_CONVERGED / PINT_NONFINITE
+ *   status  [B] int32         PINT_OK / PINT_NOT_CONVERGED / PINT_NONFINITE, or
+ *                             PINT_ERR_DEVICE if a cooperative launch's bounded
+ *                             device-side wait gave up (result unreliable)
  *
  * Plain mode (window 0): iteration k evaluates h over all steps, stops if
  * ||h||_inf < tol, otherwise applies the full Newton step.  This is the

@@ -573,7 +573,8 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, c
   if (g == 0 && tid == 0) {
     a.iters[inst] = k;
     a.resid[inst] = rg;
-    a.status[inst] = st;
+    // a bounded wait that gave up (error word) makes the result unreliable
+    a.status[inst] = co_load(&c->err) ? ST_DEVICE : st;
   }
 }
 
