@@ -3,7 +3,7 @@ Newton solver on one MI355X.
 
 Workload (default): Lorenz-96, d = 40, F = 8, RK4 dt = 0.005, T = 65536 steps,
 one instance, x0 = F + N(0, 0.01^2) (seed 2), FP64, stop when the max-abs
-residual < 1e-10, windowed Newton (window 32).  One "step" of the benchmark
+residual < 1e-10, windowed Newton (the window the autotuner picks among 32, 48, 56, 64).  One "step" of the benchmark
 is one whole solve: from the constant initial iterate to convergence, inputs
 resident in HBM.  The sequential RK4 integrator on the GPU is timed beside it
 (the comparator), and the same solve in FP32.  The CPU oracle is timed on a

@@ -165,7 +165,7 @@ def tune_scan(d: int, B: int, N: int, dtype: int = F64, *, tiles: Sequence[int] 
 
 
 def tune_window(system, x0: torch.Tensor, params: torch.Tensor, dt: float, T: int, *,
-                tol: float = 1e-10, guard: float = 1e6, windows: Sequence[int] = (32, 48, 64),
+                tol: float = 1e-10, guard: float = 1e6, windows: Sequence[int] = (32, 48, 56, 64),
                 reps: int = 1, cache: Optional[str] = DEFAULT_CACHE, force: bool = False,
                 stream=None) -> dict:
     """Pick the Newton window W of a uniform-horizon solve (pint_solve): the

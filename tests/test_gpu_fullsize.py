@@ -17,7 +17,7 @@ def _t(a, dtype=torch.float64):
     return torch.tensor(np.asarray(a), dtype=dtype, device=DEV)
 
 
-@pytest.mark.parametrize("window", [32, 48, 64])
+@pytest.mark.parametrize("window", [32, 48, 56, 64])
 def test_lorenz96_full_horizon(pint, orc, window):
     """Lorenz-96 d=40, T=65536: every window the bench's tuner may pick."""
     w = W.lorenz96(T=65536)
