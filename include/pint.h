@@ -252,7 +252,12 @@ pint_status pint_elements(const pint_system* sys, int64_t B, const void* x0,
  * zero), written as z [B][N][d] (z[n] = z_{n+1}).  A [B][N][d][d],
  * b [B][N][d].  Single-pass decoupled-lookback scan over tiles of `tile`
  * elements (0 = default); workspace from pint_scan_workspace_bytes.
- * Supported d: 1..8, 16, 32, 40, 64, 128. */
+ * Supported d: 1..8, 16, 32, 40, 64, 128.  z must not overlap A, b, z0 or
+ * the workspace (the elements are read twice, once per pass).  Returns
+ * PINT_OK at once when B or N is 0; PINT_ERR_INVALID_ARG for d < 1,
+ * negative sizes or tile, another dtype, or a NULL A, b or z;
+ * PINT_ERR_UNSUPPORTED for a d outside the list; PINT_ERR_WORKSPACE when
+ * ws is NULL or smaller than the query. */
 size_t pint_scan_workspace_bytes(int32_t d, int64_t B, int64_t N, int32_t tile,
                                  int32_t dtype);
 pint_status pint_affine_scan(int32_t d, int64_t B, int64_t N, int32_t dtype,

@@ -129,3 +129,26 @@ def test_launch_shape_and_graph_argument_checks():
     assert h.value is None
     assert lib.pint_graph_launch(None, None) == P.ERR_INVALID_ARG
     assert lib.pint_graph_destroy(None) == P.ERR_INVALID_ARG
+
+
+def test_affine_scan_argument_checks():
+    """pint_affine_scan's error returns, each decided before any HIP call
+    (the pointers below are never dereferenced)."""
+    import paper_2511_01465_amd as P
+    lib = P.load()
+    fake = ctypes.c_void_p(256)
+    scan = lambda d, B, N, dtype, A, b, z, tile, ws, nbytes: lib.pint_affine_scan(
+        d, B, N, dtype, A, b, None, z, tile, ws, nbytes, None)
+    assert scan(3, 0, 16, P.F64, None, None, None, 0, None, 0) == P.OK        # empty batch
+    assert scan(3, 1, 0, P.F64, None, None, None, 0, None, 0) == P.OK        # empty sequences
+    assert scan(0, 1, 16, P.F64, fake, fake, fake, 0, None, 0) == P.ERR_INVALID_ARG
+    assert scan(3, -1, 16, P.F64, fake, fake, fake, 0, None, 0) == P.ERR_INVALID_ARG
+    assert scan(3, 1, 16, P.F64, fake, fake, fake, -1, None, 0) == P.ERR_INVALID_ARG
+    assert scan(3, 1, 16, 7, fake, fake, fake, 0, None, 0) == P.ERR_INVALID_ARG
+    assert scan(3, 1, 16, P.F64, None, fake, fake, 0, None, 0) == P.ERR_INVALID_ARG
+    assert scan(9, 1, 16, P.F64, fake, fake, fake, 0, fake, 1 << 20) == P.ERR_UNSUPPORTED
+    assert lib.pint_scan_workspace_bytes(9, 1, 16, 0, P.F64) == 0
+    need = lib.pint_scan_workspace_bytes(3, 1, 16, 0, P.F64)
+    assert need > 0
+    assert scan(3, 1, 16, P.F64, fake, fake, fake, 0, None, need) == P.ERR_WORKSPACE
+    assert scan(3, 1, 16, P.F64, fake, fake, fake, 0, fake, need - 1) == P.ERR_WORKSPACE
