@@ -109,12 +109,16 @@ constexpr int vec_width(int run) {
 
 // Tile shape of the small-d scan: NT threads, S consecutive elements per
 // thread, the tile staged in LDS within a 48 KiB budget (three workgroups
-// per compute unit).  RA / RB: scalars of A / b per thread run.
+// per compute unit).  RA / RB: scalars of A / b per thread run.  FP32 runs
+// are sized as FP64 ones (half the budget) for d = 1 and 3, measured faster
+// there (2^24 elements: d = 1 0.091 -> 0.078 ms, d = 3 0.587 -> 0.463 ms),
+// and by their own size for d = 2 (0.195 ms against 0.205 ms).
 template <int D, typename T>
 struct SmallShape {
   static constexpr int NT = D <= 4 ? 256 : 64;
   static constexpr int E = D * D + D;
-  static constexpr int S0 = 49152 / (E * (int)sizeof(T) * NT);
+  static constexpr int SB = D == 2 ? (int)sizeof(T) : 8;  // bytes counted per scalar
+  static constexpr int S0 = 49152 / (E * SB * NT);
   static constexpr int S = S0 < 1 ? 1 : (S0 > 16 ? 16 : S0);
   static constexpr int CH = NT * S;   // elements per chunk (one LDS staging)
   static constexpr int C = D == 1 ? 12 : 8;  // chunks per tile (one lookback per tile)
