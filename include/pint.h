@@ -125,6 +125,18 @@ typedef struct {
                           /* skipped; NULL = 0, 1, ..., B-1                     */
 } pint_options;
 
+/* Bound of the device-side waits of the cooperative solvers (pint_solve of
+ * dense dimensions in windowed mode, and of a few long small-d instances in
+ * plain mode), in polls of the awaited flag, each followed by the shortest
+ * sleep.  When a wait gives up, every workgroup of the instance leaves its
+ * Newton loop at its next wait, and the instance's status is
+ * PINT_ERR_DEVICE (its result is unreliable).  polls = 0 makes every such
+ * wait give up at once, without polling: callers that test the error path
+ * force it this way.  Process-wide; applies to launches enqueued after the
+ * call; the default is PINT_WAIT_LIMIT_DEFAULT. */
+#define PINT_WAIT_LIMIT_DEFAULT 268435456ull
+void pint_set_wait_limit(uint64_t polls);
+
 /* Number of parameters of `system` at dimension d, or -1 if not allowed. */
 int pint_n_params(int32_t system, int32_t d);
 

@@ -262,14 +262,19 @@ int orc_ftheta(int sys, int d, const double* P, const double* x, double* G) {
 /* a21 = a32 = 1/2, a43 = 1, b = (1/6, 1/3, 1/3, 1/6)                     */
 /* ---------------------------------------------------------------------- */
 
-/* Small dense helpers: C = A B for d x d (row-major), y = A x. */
+/* Small dense helpers: C = A B for d x d (row-major), y = A x.  Every
+ * entry C_ij is summed from 0 over k = 0, 1, ..., d-1 in that order (the
+ * k loop sits outside the j loop only so that B is read row by row). */
 static void matmul(int d, const double* A, const double* B, double* C) {
-  for (int i = 0; i < d; i++)
-    for (int j = 0; j < d; j++) {
-      double acc = 0.0;
-      for (int k = 0; k < d; k++) acc += A[i * d + k] * B[k * d + j];
-      C[i * d + j] = acc;
+  for (int i = 0; i < d; i++) {
+    double* c = C + (size_t)i * d;
+    for (int j = 0; j < d; j++) c[j] = 0.0;
+    for (int k = 0; k < d; k++) {
+      const double a = A[i * d + k];
+      const double* b = B + (size_t)k * d;
+      for (int j = 0; j < d; j++) c[j] += a * b[j];
     }
+  }
 }
 
 static void matvec(int d, const double* A, const double* x, double* y) {

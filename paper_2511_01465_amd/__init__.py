@@ -60,7 +60,10 @@ EXPORTS = ["pint_n_params", "pint_status_string", "pint_supported", "pint_worksp
            "pint_elements", "pint_scan_workspace_bytes", "pint_affine_scan",
            "pint_scan_band_workspace_bytes", "pint_affine_scan_band",
            "pint_adjoint_workspace_bytes", "pint_adjoint", "pint_graph_capture_varlen",
-           "pint_graph_launch", "pint_graph_destroy"]
+           "pint_graph_launch", "pint_graph_destroy", "pint_set_wait_limit"]
+
+# include/pint.h: PINT_WAIT_LIMIT_DEFAULT
+WAIT_LIMIT_DEFAULT = 268435456
 
 
 def load(path: str = LIB_PATH):
@@ -94,6 +97,7 @@ def load(path: str = LIB_PATH):
                                                 C.POINTER(C.c_void_p)]),
         "pint_graph_launch": (C.c_int, [vp, vp]),
         "pint_graph_destroy": (C.c_int, [vp]),
+        "pint_set_wait_limit": (None, [C.c_uint64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -260,6 +264,10 @@ def pint_graph_launch(handle, stream=None) -> int:
 
 def pint_graph_destroy(handle) -> int:
     return load().pint_graph_destroy(handle)
+
+
+def pint_set_wait_limit(polls: int) -> None:
+    load().pint_set_wait_limit(int(polls))
 
 
 # ---------------------------------------------------------- conveniences --
@@ -503,14 +511,23 @@ def adjoint(system, x0, params, dt, traj, g, seg: int = 0, with_params: bool = T
 class SolveFn(torch.autograd.Function):
     """traj = SolveFn.apply(x0 [B,d], params [B,np], system, dt, T, tol, window, seg).
 
-    Forward: Newton solve (pint_solve).  Backward: the reverse-time adjoint
+    Forward: Newton solve (pint_solve); raises PintError unless every
+    instance converged (the adjoint is that of the discrete solution map, so
+    it is only meaningful at a root of h).  Backward: the reverse-time adjoint
     scan (pint_adjoint) through the discrete RK4 map at the returned
-    trajectory, giving dL/dx0 and dL/dparams."""
+    trajectory, giving dL/dx0, and dL/dparams when params requires a
+    gradient."""
 
     @staticmethod
     def forward(ctx, x0, params, system, dt, T, tol=1e-10, window=0, seg=0):
         traj, iters, resid, status = solve(system, x0.detach(), params.detach(), dt, T, tol=tol,
                                            window=window)
+        st = status.reshape(-1)
+        bad = (st != OK).nonzero()
+        if bad.numel():
+            b = int(bad[0, 0])
+            raise PintError(f"SolveFn: instance {b} ended with status {int(st[b])} "
+                            f"({status_string(int(st[b]))}); no gradient at a non-root")
         ctx.save_for_backward(x0.detach(), params.detach(), traj)
         ctx.system, ctx.dt, ctx.seg = system, dt, seg
         ctx.mark_non_differentiable(iters, resid, status)
@@ -520,7 +537,9 @@ class SolveFn(torch.autograd.Function):
     def backward(ctx, g_traj, *_):
         x0, params, traj = ctx.saved_tensors
         g = torch.zeros_like(traj) if g_traj is None else g_traj.contiguous()
-        gx0, gth = adjoint(ctx.system, x0, params, ctx.dt, traj, g, seg=ctx.seg)
-        if params.dim() == 1:
+        want_th = bool(ctx.needs_input_grad[1])
+        gx0, gth = adjoint(ctx.system, x0, params, ctx.dt, traj, g, seg=ctx.seg,
+                           with_params=want_th)
+        if gth is not None and params.dim() == 1:
             gth = gth.sum(0)
         return gx0, gth, None, None, None, None, None, None

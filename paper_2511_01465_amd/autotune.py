@@ -16,6 +16,7 @@ work by the largest factor, so it goes first).
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 from typing import Optional, Sequence
@@ -26,6 +27,36 @@ from . import (F64, F32, PintError, _dtype_code, _sys_id, longest_first, pint_af
                pint_scan_workspace_bytes, solve_varlen)
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pint", "autotune.json")
+
+
+_BUILD_ID = None
+
+
+def _build_id() -> str:
+    """Digest of the loaded libpint.so: a rebuilt kernel invalidates old picks."""
+    global _BUILD_ID
+    if _BUILD_ID is None:
+        from . import LIB_PATH
+        h = hashlib.sha256()
+        with open(LIB_PATH, "rb") as f:
+            for blk in iter(lambda: f.read(1 << 20), b""):
+                h.update(blk)
+        _BUILD_ID = h.hexdigest()[:16]
+    return _BUILD_ID
+
+
+def _digest(*tensors) -> str:
+    """Digest of tensor contents (initial states, parameters, horizons)."""
+    h = hashlib.sha256()
+    for t in tensors:
+        t = torch.as_tensor(t)
+        h.update(str((tuple(t.shape), str(t.dtype))).encode())
+        h.update(t.detach().cpu().contiguous().numpy().tobytes())
+    return h.hexdigest()[:16]
+
+
+def _cands(values) -> str:
+    return ",".join(str(v) for v in values)
 
 
 def _device_name(device) -> str:
@@ -67,12 +98,17 @@ def _time_ms(fn, reps: int, stream) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def varlen_key(system, x0: torch.Tensor, lengths, dt: float, tol: float, guard: float) -> str:
+def varlen_key(system, x0: torch.Tensor, lengths, dt: float, tol: float, guard: float,
+               params=None, candidates=()) -> str:
+    """Cache key: the workload (sizes, a digest of x0, params and the
+    horizons), the candidate lists, the device and the library build."""
     lengths = torch.as_tensor(lengths, dtype=torch.int64)
     B, d = x0.shape
-    return "varlen|sys=%d|d=%d|dtype=%d|B=%d|sumT=%d|maxT=%d|dt=%g|tol=%g|guard=%g|%s" % (
+    data = _digest(x0, lengths, *(() if params is None else (params,)))
+    cands = "|".join(_cands(c) for c in candidates)
+    return "varlen|sys=%d|d=%d|dtype=%d|B=%d|sumT=%d|maxT=%d|dt=%g|tol=%g|guard=%g|data=%s|cand=%s|%s|lib=%s" % (
         _sys_id(system), d, _dtype_code(x0), B, int(lengths.sum()), int(lengths.max()) if B else 0,
-        dt, tol, guard, _device_name(x0.device))
+        dt, tol, guard, data, cands, _device_name(x0.device), _build_id())
 
 
 def tune_varlen(system, x0: torch.Tensor, params: torch.Tensor, dt: float, lengths, *,
@@ -87,7 +123,8 @@ def tune_varlen(system, x0: torch.Tensor, params: torch.Tensor, dt: float, lengt
     with those keys plus "ms" (the winner's time) and "trials" (every
     configuration timed, in order).  Plain mode (window 0) is not a
     candidate: on these workloads it does not converge in practice."""
-    key = varlen_key(system, x0, lengths, dt, tol, guard)
+    key = varlen_key(system, x0, lengths, dt, tol, guard, params,
+                     (windows, blocks, wg_per_cu, orders))
     store = _load_cache(cache)
     if not force and key in store:
         return store[key]
@@ -136,7 +173,8 @@ def tune_scan(d: int, B: int, N: int, dtype: int = F64, *, tiles: Sequence[int] 
     if d <= 8:
         return {"tile": 0, "ms": None, "trials": []}
     tdt = torch.float64 if dtype == F64 else torch.float32
-    key = "scan|d=%d|B=%d|N=%d|dtype=%d|%s" % (d, B, N, dtype, _device_name(device))
+    key = "scan|d=%d|B=%d|N=%d|dtype=%d|cand=%s|%s|lib=%s" % (d, B, N, dtype, _cands(tiles),
+                                                              _device_name(device), _build_id())
     store = _load_cache(cache)
     if not force and key in store:
         return store[key]
@@ -173,9 +211,9 @@ def tune_window(system, x0: torch.Tensor, params: torch.Tensor, dt: float, T: in
     costs more per update and needs fewer updates, up to the point where the
     linearisation across it fails and the guard keeps cutting updates."""
     from . import solve
-    key = "window|sys=%d|d=%d|dtype=%d|B=%d|T=%d|dt=%g|tol=%g|guard=%g|%s" % (
+    key = "window|sys=%d|d=%d|dtype=%d|B=%d|T=%d|dt=%g|tol=%g|guard=%g|data=%s|cand=%s|%s|lib=%s" % (
         _sys_id(system), x0.shape[-1], _dtype_code(x0), x0.shape[0] if x0.dim() > 1 else 1, T, dt,
-        tol, guard, _device_name(x0.device))
+        tol, guard, _digest(x0, params), _cands(windows), _device_name(x0.device), _build_id())
     store = _load_cache(cache)
     if not force and key in store:
         return store[key]

@@ -91,11 +91,17 @@ SolveArgs make_args(const pint_system* sys, int64_t B, const void* x0, double dt
   return a;
 }
 
+uint64_t g_wait_limit = PINT_WAIT_LIMIT_DEFAULT;
+
 }  // namespace
+
+uint64_t pint::wait_limit() { return __atomic_load_n(&g_wait_limit, __ATOMIC_RELAXED); }
 
 extern "C" {
 
 int pint_n_params(int32_t system, int32_t d) { return n_params_of(system, d); }
+
+void pint_set_wait_limit(uint64_t polls) { __atomic_store_n(&g_wait_limit, polls, __ATOMIC_RELAXED); }
 
 const char* pint_status_string(int32_t s) {
   switch (s) {

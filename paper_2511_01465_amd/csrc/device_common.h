@@ -227,4 +227,24 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
             (unsigned long long)__double_as_longlong(v));
 }
 
+// Bounded wait of one thread on a cross-workgroup condition.  Polls `ready`
+// (device-coherent loads inside it) and the instance's error word `err`,
+// which any workgroup raises when one of its own waits gives up.  Returns
+// false once `ready` holds; true when the error word is set, or when
+// `limit` polls have gone by, in which case it raises the error word itself
+// (limit 0: at once, without polling).  A caller that gets true must not use
+// anything the awaited workgroups publish, and leaves its loop.
+template <class F>
+__device__ __forceinline__ bool bounded_wait(uint32_t* err, uint64_t limit, F&& ready) {
+  for (uint64_t it = 0;; it++) {
+    if (it >= limit) {
+      atomicOr(err, 1u);
+      return true;
+    }
+    if (ready()) return false;
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 }  // namespace pint

@@ -65,6 +65,10 @@ int affine_scan_band(int d, int bw, int boff, int64_t B, int64_t N, int dtype, c
 size_t adjoint_ws_bytes(int system, int d, int64_t B, int64_t T, int64_t seg, int dtype);
 int adjoint(const SolveArgs& a, const void* g, void* dL_dx0, void* dL_dth, int64_t seg);
 
+// Polls before a cross-workgroup wait of the cooperative solvers gives up
+// (process-wide; set through pint_set_wait_limit).
+uint64_t wait_limit();
+
 // Zero `n` 32-bit words with a kernel (no memset nodes in captured graphs).
 int fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 

@@ -29,6 +29,7 @@ struct DenseKArgs {
   void* ws_elems;        // per workgroup slot: AT [Wt][D][D], b [Wt][D], dx [Wt][D], hn [Wt]
   int64_t Wt;            // elements per slot (window + slack, or T in plain mode)
   int64_t slot_stride;   // scalars between consecutive workgroup slots
+  uint64_t wait_limit;   // polls before a cross-workgroup wait gives up
 };
 
 // Slot: AT [Wt][D][D] (or the band), b [Wt][D], dx [Wt][D], then the
@@ -660,52 +661,51 @@ struct CoopCtl {
 static_assert(sizeof(CoopCtl) == 64, "control block size");
 
 // Barrier among the G workgroups of one instance.  Release fence before
-// arriving, acquire fence after leaving; the wait is bounded.
-__device__ __forceinline__ void coop_barrier(CoopCtl* c, int G, uint32_t& gen) {
+// arriving, acquire fence after leaving.  The wait is bounded
+// (bounded_wait); returns, in every thread, true if the instance's error
+// word was seen (a wait of this or another workgroup gave up): the caller
+// then leaves its round loop.
+__device__ __forceinline__ bool coop_barrier(CoopCtl* c, int G, uint32_t& gen, uint64_t limit) {
+  __shared__ int s_fail;
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
     const uint32_t target = gen + 1;
     const uint32_t prev = atomicAdd(&c->bar_count, 1u);
+    bool fail = false;
     if (prev == (uint32_t)(G - 1)) {
       __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __threadfence();
       __hip_atomic_store(&c->bar_gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      for (uint64_t it = 0;
-           __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target; it++) {
-        if (it > (1ull << 28)) {
-          atomicOr(&c->err, 1u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
+      fail = bounded_wait(&c->err, limit, [&] {
+        return __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == target;
+      });
     }
     __threadfence();
     gen = target;
+    s_fail = fail;
   }
   __syncthreads();
+  return s_fail != 0;
 }
 
-// One-way signals of a round (thread 0 of a workgroup; bounded waits raise
-// the error word and give up).  Every workgroup releases its elements by
-// incrementing `arrive`; only workgroup 0 waits for all of them.  Workgroup
-// 0 releases the committed update by storing the round in `go`; only the
-// others wait for it.
+// One-way signals of a round (thread 0 of a workgroup).  Every workgroup
+// releases its elements by incrementing `arrive`; only workgroup 0 waits for
+// all of them.  Workgroup 0 releases the committed update by storing the
+// round in `go`; only the others wait for it.  The wait returns true when
+// the error word was seen (see bounded_wait).
 __device__ __forceinline__ void coop_arrive(CoopCtl* c) {
   __threadfence();
   atomicAdd(&c->arrive, 1u);
 }
-__device__ __forceinline__ void coop_wait_at_least(CoopCtl* c, const uint32_t* word, uint32_t target) {
-  for (uint64_t it = 0;
-       __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; it++) {
-    if (it > (1ull << 28)) {
-      atomicOr(&c->err, 1u);
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
+__device__ __forceinline__ bool coop_wait_at_least(CoopCtl* c, const uint32_t* word, uint32_t target,
+                                                   uint64_t limit) {
+  const bool fail = bounded_wait(&c->err, limit, [&] {
+    return __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+  });
   __threadfence();
+  return fail;
 }
 __device__ __forceinline__ void coop_release_go(CoopCtl* c, uint32_t round) {
   __threadfence();
@@ -783,8 +783,11 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
       c->done = done;
     }
   };
-  coop_barrier(c, G, gen);  // initial iterate written everywhere
-  if (g == 0) {
+  const uint64_t lim = a.wait_limit;
+  __shared__ int s_fail;
+  // a wait that gave up (error word) ends the solve in every workgroup
+  bool fail = coop_barrier(c, G, gen, lim);  // initial iterate written everywhere
+  if (!fail && g == 0) {
     if constexpr (SPEC) {
       if (tid == 0) {
         c->lo = 1;
@@ -794,23 +797,40 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
       decide(1);
     }
   }
-  coop_barrier(c, G, gen);
-  for (uint32_t rnd = 1;; rnd++) {
+  if (!fail) fail = coop_barrier(c, G, gen, lim);
+  for (uint32_t rnd = 1; !fail; rnd++) {
     if (tid == 0) {
       s_win[0] = c->lo;
       s_win[1] = c->hi;
       s_done = c->done;
+      // the error word, loaded with the window: a workgroup that gave up
+      // may have left the window unset
+      s_fail = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      const int64_t lo = s_win[0], hi = SPEC ? lo : s_win[1];
+      if (!s_done && !s_fail && !(lo >= 1 && lo <= Tn && hi >= lo && hi <= Tn)) {
+        atomicOr(&c->err, 1u);  // never for a consistent control block
+        s_fail = 1;
+      }
     }
     __syncthreads();
-    if (s_done) break;
+    if (s_done || s_fail) break;
     const int64_t base = s_win[0];
     const int64_t slen = SPEC ? ((Tn - base + 1) < Wcap ? (Tn - base + 1) : Wcap) : s_win[1] - base + 1;
     dn_elements<T, S>(sm, dt, X, base, slen, g, G, AT, bb, SPEC ? hn : nullptr);
     __syncthreads();  // this workgroup's element stores are issued
     if (tid == 0) coop_arrive(c);
     if (g == 0) {
-      if (tid == 0) coop_wait_at_least(c, &c->arrive, (uint32_t)G * rnd);
+      if (tid == 0) s_fail = coop_wait_at_least(c, &c->arrive, (uint32_t)G * rnd, lim);
       __syncthreads();
+      if (s_fail) {
+        // some elements may be missing: no update; release the others, who
+        // find the solve done
+        if (tid == 0) {
+          c->done = 1;
+          coop_release_go(c, rnd);
+        }
+        break;
+      }
       int64_t p = base, next = 0;
       int done = 0;
       bool fold = true;
@@ -882,19 +902,22 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
       __syncthreads();  // the committed update and the next window are written
       if (tid == 0) coop_release_go(c, rnd);
     } else {
-      if (tid == 0) coop_wait_at_least(c, &c->go, rnd);
+      if (tid == 0) s_fail = coop_wait_at_least(c, &c->go, rnd, lim);
       __syncthreads();
+      if (s_fail) break;
     }
   }
   // final residual: steps split over the G workgroups
   const double r = dn_resid_max<T, S>(sm, dt, X, Tn, 1 + g, G);
   if (tid == 0) atomic_max_nonneg(reinterpret_cast<double*>(&c->rmax), r);
-  coop_barrier(c, G, gen);
+  (void)coop_barrier(c, G, gen, lim);
   if (g == 0 && tid == 0) {
     a.iters[inst] = k;
     a.resid[inst] = __longlong_as_double((long long)__hip_atomic_load(&c->rmax, __ATOMIC_RELAXED,
                                                                       __HIP_MEMORY_SCOPE_AGENT));
-    a.status[inst] = c->err ? ST_DEVICE : st;
+    // a wait that gave up (error word) makes the result unreliable
+    a.status[inst] = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                         ? ST_DEVICE : st;
   }
 }
 
@@ -1045,6 +1068,7 @@ static DenseKArgs to_dk(const SolveArgs& a) {
   k.iters = a.iters;
   k.resid = a.resid;
   k.status = a.status;
+  k.wait_limit = wait_limit();
   return k;
 }
 

@@ -30,6 +30,7 @@ struct SmallKArgs {
   int32_t* status;
   uint32_t* queue;
   const int64_t* order;  // [B] instance taken at each queue slot, or nullptr
+  uint64_t wait_limit;   // cooperative solver: polls before a wait gives up
 };
 
 template <typename T, int D>
@@ -246,9 +247,12 @@ constexpr int LINE_U32 = 16;
 // Two-level barrier among the G workgroups of one instance: a workgroup
 // arrives on its group's counter; the last of a group arrives on the top
 // counter; the last of those resets the counters and raises the generation
-// that everyone waits for.  Every wait is bounded (the error word is raised
-// and the wave goes on).
-__device__ __forceinline__ void coop_sync(SmallCtl* c, uint32_t* grp, int G, int g, uint32_t& gen) {
+// that everyone waits for.  The wait is bounded (bounded_wait); returns, in
+// every thread, true if the instance's error word was seen (a wait of this
+// or another workgroup gave up), and the caller leaves its loop.
+__device__ __forceinline__ bool coop_sync(SmallCtl* c, uint32_t* grp, int G, int g, uint32_t& gen,
+                                          uint64_t limit) {
+  __shared__ int s_fail;
   __syncthreads();
   if (threadIdx.x == 0) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's posts are complete
@@ -269,17 +273,13 @@ __device__ __forceinline__ void coop_sync(SmallCtl* c, uint32_t* grp, int G, int
         released = true;
       }
     }
-    if (!released)
-      for (uint64_t it = 0; co_load(&c->gen) != target; it++) {
-        if (it > (1ull << 28)) {
-          atomicOr(&c->err, 1u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
+    bool fail = false;
+    if (!released) fail = bounded_wait(&c->err, limit, [&] { return co_load(&c->gen) == target; });
     gen = target;
+    s_fail = fail;
   }
   __syncthreads();
+  return s_fail != 0;
 }
 
 // Workspace of the cooperative solver, per instance (offsets in bytes from
@@ -334,6 +334,7 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, c
   __shared__ T s_z[D], s_xprev[D], s_xlast[D], s_zlast[D], s_xb[D];
   __shared__ Aff<T, D> s_run;
   __shared__ Aff<T, D> s_cagg[KR];
+  __shared__ int s_fail;
   const int tid = threadIdx.x;
   const int64_t inst = blockIdx.x / G;
   const int g = (int)(blockIdx.x % G);
@@ -385,14 +386,10 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, c
     // ---- A: residual maximum and composition of this workgroup's elements
     if (k > 0 && g > 0 && lo <= hi) {
       if (tid == 0)  // the state workgroup g-1 published at the end of iteration k-1
-        for (uint64_t it = 0; co_load(&bflag[(g - 1) * LINE_U32]) < (uint32_t)k; it++) {
-          if (it > (1ull << 28)) {
-            atomicOr(&c->err, 1u);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
+        s_fail = bounded_wait(&c->err, a.wait_limit,
+                              [&] { return co_load(&bflag[(g - 1) * LINE_U32]) >= (uint32_t)k; });
       __syncthreads();
+      if (s_fail) { st = ST_DEVICE; break; }
       if (tid < D) s_xb[tid] = co_load(&bnd[((1 - par) * G + (g - 1)) * D + tid]);
     }
     if (tid == 0) aff_identity(s_run);
@@ -445,7 +442,7 @@ __global__ __launch_bounds__(NT) void k_newton_small_coop(SmallKArgs a, int G, c
     if (tid < D * D) co_store(&post_agg[(par * G + g) * E + tid], s_run.A[tid]);
     if (tid < D) co_store(&post_agg[(par * G + g) * E + D * D + tid], s_run.b[tid]);
     if (tid == 0) co_store(&post_r[par * G + g], r);
-    coop_sync(c, grp, G, g, gen);
+    if (coop_sync(c, grp, G, g, gen, a.wait_limit)) { st = ST_DEVICE; break; }
 
     // ---- B: global residual and stop test; dx at the start of this range
     double rr = 0.0;

@@ -45,6 +45,7 @@ static SmallKArgs to_k(const SolveArgs& a) {
   k.resid = a.resid;
   k.status = a.status;
   k.order = a.order;
+  k.wait_limit = wait_limit();
   return k;
 }
 

@@ -111,7 +111,7 @@ constexpr int vec_width(int run) {
 // thread, the tile staged in LDS within a 48 KiB budget (three workgroups
 // per compute unit).  RA / RB: scalars of A / b per thread run.  FP32 runs
 // are sized as FP64 ones (half the budget) for d = 1 and 3, measured faster
-// there (2^24 elements: d = 1 0.091 -> 0.078 ms, d = 3 0.587 -> 0.463 ms),
+// there (2^24 elements: d = 1 0.092 -> 0.086 ms, d = 3 0.586 -> 0.449 ms),
 // and by their own size for d = 2 (0.195 ms against 0.205 ms).
 template <int D, typename T>
 struct SmallShape {

@@ -125,3 +125,22 @@ def test_solvefn_autograd(pint, orc):
         rx0, rth = orc.adjoint(w.system, w.params[b], w.dt, w.x0[b], tr[b], g)
         assert np.abs(x0.grad[b].cpu().numpy() - rx0).max() <= 1e-10 * max(1.0, np.abs(rx0).max())
         assert abs(float(P.grad[b, 0]) - rth[0]) <= 1e-10 * max(1.0, abs(rth[0]))
+
+
+def test_solvefn_x0_only_kuramoto(pint, orc):
+    """Parameters that need no gradient are not differentiated: Kuramoto,
+    whose parameter derivative is not built, gives dL/dx0 through SolveFn,
+    equal to the oracle's adjoint on the returned trajectory."""
+    w = W.kuramoto(B=2, T=128, window=64)
+    x0 = _t(w.x0).requires_grad_(True)
+    P = _t(w.params)
+    traj, iters, resid, status = pint.SolveFn.apply(x0, P, pint.KURAMOTO, w.dt, 128, 1e-12, 64, 0)
+    rng = np.random.default_rng(7)
+    gt = rng.normal(size=traj.shape)
+    (traj * _t(gt)).sum().backward()
+    torch.cuda.synchronize()
+    assert P.grad is None and torch.all(status == 0)
+    tr = traj.detach().cpu().numpy()
+    for b in range(w.B):
+        rx0, _ = orc.adjoint(w.system, w.params[b], w.dt, w.x0[b], tr[b], gt[b], with_theta=False)
+        assert np.abs(x0.grad[b].cpu().numpy() - rx0).max() <= 1e-10 * max(1.0, np.abs(rx0).max())

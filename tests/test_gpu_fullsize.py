@@ -56,20 +56,46 @@ def test_vdp_batch_tuned_graph(pint, orc, tmp_path):
     T_off = g.T_off.cpu().numpy()
     traj = g.traj.cpu().numpy()
     rng = np.random.default_rng(11)
-    for b in rng.choice(w.B, 6, replace=False):
+    # six random instances plus the three longest with mu above 4.5 (the
+    # stiffest, longest solves: the most updates)
+    stiff = [b for b in np.argsort(-w.T) if w.params[b, 0] > 4.5][:3]
+    pick = list(rng.choice(w.B, 6, replace=False)) + [int(b) for b in stiff]
+    iters = g.iters.cpu().numpy()
+
+    def run(b):
+        return orc.newton(w.system, w.params[b], w.dt, int(w.T[b]), w.x0[b], tol=1e-10,
+                          window=cfg["window"], max_iter=4 * int(w.T[b]))
+
+    refs = orc.map_instances(run, pick)
+    for b, r in zip(pick, refs):
         tb = traj[T_off[b]:T_off[b + 1]]
         h = orc.residual(w.system, w.params[b], w.dt, w.x0[b], tb)
         assert np.abs(h).max() < 1e-10, b
-        r = orc.newton(w.system, w.params[b], w.dt, int(w.T[b]), w.x0[b], tol=1e-10,
-                       window=cfg["window"], max_iter=4 * int(w.T[b]))
         assert r["status"] == 0
-        assert abs(int(g.iters[b]) - r["iters"]) <= 1, (b, int(g.iters[b]), r["iters"])
+        dk = abs(int(iters[b]) - r["iters"])
+        assert dk == 0 or (dk == 1 and np.min(r["hist"][-3:]) < 100 * 1e-10), \
+            (b, int(iters[b]), r["iters"])
+        # same iterate: 1e-10 max-abs, or within ||H^-1|| (r1 + r2) when the
+        # neutral phase direction carries the two iterates apart
+        err = float(np.abs(tb - r["traj"]).max())
+        if err > 1e-10:
+            from test_gpu_small import hinv_norm
+            hn = hinv_norm(orc, w.system, w.params[b], w.dt, w.x0[b], r["traj"])
+            bound = hn * (float(g.resid[b]) + r["final_resid"])
+            assert err <= bound, (b, err, bound)
+        print(f"[full] vdp b={b} T={int(w.T[b])} mu={w.params[b, 0]:.2f} updates "
+              f"{int(iters[b])} (oracle {r['iters']}) max|gpu-oracle| {err:.2e}", flush=True)
     g.close()
 
 
+@pytest.mark.timeout(900)
 def test_kuramoto_full(pint, orc):
-    """Kuramoto d=128, 8 x 4096, W=256: status of all, FP64 defect of every
-    step of three sampled instances."""
+    """Kuramoto d=128, 8 x 4096, W=256 (the benchmark's launch): every
+    instance against the oracle's windowed Newton on the same inputs (all
+    eight on the host's cores at once): status and update count equal, the
+    FP64 defect of every step below tol, and the iterates the same to 1e-10
+    max-abs (the only neutral direction, the global phase, carries rounding
+    additively, not exponentially)."""
     w = W.kuramoto()
     print("[full] kuramoto 8 x 4096", flush=True)
     traj, iters, resid, status = pint.solve(pint.KURAMOTO, _t(w.x0), _t(w.params), w.dt, 4096,
@@ -77,9 +103,21 @@ def test_kuramoto_full(pint, orc):
     torch.cuda.synchronize()
     assert bool((status == 0).all())
     tr = traj.cpu().numpy()
-    for b in (0, 3, 7):
+
+    def run(b):
+        return orc.newton(w.system, w.params[b], w.dt, 4096, w.x0[b], tol=1e-10, window=256,
+                          max_iter=4097)
+
+    print("[full] kuramoto oracle, 8 instances", flush=True)
+    refs = orc.map_instances(run, list(range(w.B)))
+    for b, ref in enumerate(refs):
         h = orc.residual(w.system, w.params[b], w.dt, w.x0[b], tr[b])
+        err = float(np.abs(tr[b] - ref["traj"]).max())
+        print(f"[full] kuramoto b={b} updates {int(iters[b])} (oracle {ref['iters']}) "
+              f"defect {np.abs(h).max():.2e} max|gpu-oracle| {err:.2e}", flush=True)
+        assert ref["status"] == 0 and int(iters[b]) == ref["iters"], b
         assert np.abs(h).max() < 1e-10, b
+        assert err <= 1e-10, b
 
 
 def test_adjoint_full_sampled(pint, orc):

@@ -59,6 +59,47 @@ def test_dense_d_several_tiles_ragged(pint, orc, d, dtype):
     _check(pint, orc, d, N, 2, dtype, True, seed=20 + d)
 
 
+# Explicit tile lengths, so that every tile folds several elements into its
+# aggregate on MFMA (FP64 16x16x4: the running product held in the
+# accumulators for even d, the augmented [[A, b], [0, 1]] product for
+# d = 40; FP32 16x16x4: the product in LDS).  128 and 256 are the tiles the
+# full-horizon dense scans run at (8 Kuramoto sequences of 4096 elements,
+# one Lorenz-96 sequence of 65536); each case has at least three tiles per
+# sequence and a ragged last tile.
+DENSE_TILES = [(16, 8), (16, 32), (32, 8), (32, 32), (40, 16), (40, 128), (40, 256),
+               (64, 8), (64, 32), (128, 16), (128, 128)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("d,tile", DENSE_TILES)
+def test_dense_fold_at_tile(pint, orc, d, tile, dtype):
+    B = 8 if (d, tile) == (128, 128) else 3
+    N = 3 * tile + 17
+    print(f"[scan] dense d={d} tile={tile} {dtype} N={N} B={B}", flush=True)
+    _check(pint, orc, d, N, B, dtype, True, seed=200 + d + tile, tile=tile)
+
+
+@pytest.mark.parametrize("d", [40, 128])
+def test_dense_fold_gauss_f32(pint, orc, d):
+    """FP32 MFMA fold on elements that are not orthogonal (entries N(0, 1/d),
+    products shrink or grow): relative 1e-4 against the FP64 recursion on the
+    same FP32-rounded elements, over 48 elements (tiles of 16)."""
+    B, N = 2, 48
+    A = np.empty((B, N, d, d))
+    b = np.empty((B, N, d))
+    for s in range(B):
+        A[s], b[s] = W.random_affine(N, d, seed=300 + d + s, kind="gauss")
+    A32, b32 = A.astype(np.float32), b.astype(np.float32)
+    z = pint.affine_scan(torch.tensor(A32, device=DEV), torch.tensor(b32, device=DEV), tile=16)
+    torch.cuda.synchronize()
+    ref = _ref(orc, A32.astype(np.float64), b32.astype(np.float64), None)
+    got = z.double().cpu().numpy()
+    for s in range(B):
+        for n in range(N):
+            scale = max(1e-30, np.abs(ref[s, n]).max())
+            assert np.abs(got[s, n] - ref[s, n]).max() <= 1e-4 * scale, (d, s, n)
+
+
 @pytest.mark.parametrize("d,N", [(3, 1), (3, 512), (40, 1), (40, 16), (40, 17), (2, 2)])
 def test_edge_lengths(pint, orc, d, N):
     _check(pint, orc, d, N, 2, "f64", False, seed=5)
