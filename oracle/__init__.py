@@ -70,6 +70,7 @@ def _load():
                                     i64p, dp]),
         "orc_adjoint": (i, [i, i, dp, d, i64, dp, dp, dp, dp, dp]),
         "orc_tangent": (i, [i, i, dp, d, i64, dp, dp, dp, dp, dp]),
+        "orc_parareal": (i, [i, i, i, dp, d, i64, i64, dp, d, i64, dp, dp, i64p, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -289,6 +290,34 @@ def tangent(sys, params, dt, x0, traj, dx0, dtheta=None):
     if rc != 0:
         raise ValueError("no parameter derivative for this system")
     return v
+
+
+def parareal_windows(N):
+    """The paper's split of N steps for Parareal (Sec. 4.1): M = floor(sqrt(N))
+    windows of S = floor(N / M) fine steps (a reading; it reproduces the
+    printed R histories)."""
+    import math
+    M = math.isqrt(int(N))
+    return (M, int(N) // M) if M > 0 else (0, 0)
+
+
+def parareal(sys, params, dt, M, S, x0, tol=1e-10, max_iter=None, method=RK4):
+    """Parareal of Sec. 2.2 with M windows of S fine steps.  Returns
+    dict(traj [M*S, d], status, iters (K, fine sweeps), final_resid, hist)."""
+    x0 = _f64(x0)
+    d = x0.size
+    M, S = int(M), int(S)
+    if max_iter is None:
+        max_iter = M + 1
+    traj = np.empty((max(M * S, 0), d))
+    hist = np.full(max(int(max_iter), 1), np.nan)
+    iters = C.c_int64(0)
+    fres = C.c_double(0.0)
+    st = _load().orc_parareal(method, sys, d, _p(_f64(params)), dt, M, S, _p(x0), tol,
+                              int(max_iter), _p(traj), _p(hist), C.byref(iters),
+                              C.byref(fres))
+    k = iters.value
+    return dict(traj=traj, status=st, iters=k, final_resid=fres.value, hist=hist[:k].copy())
 
 
 def map_instances(fn, items, threads=None):

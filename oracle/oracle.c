@@ -976,3 +976,114 @@ int orc_tangent(int sys, int d, const double* P, double dt, int64_t T,
   free(prevv);
   return rc;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Parareal, the comparison method of Sec. 2.2                             */
+/* ---------------------------------------------------------------------- */
+
+/* One step of the rule `method` from x to out with step size h: the RK4 map
+ * Phi for ORC_RK4, else the implicit step solved by orc_integrate_implicit.
+ * Returns 0, or -1 if an implicit step did not converge. */
+static int one_step(int method, int sys, int d, const double* P, double h,
+                    const double* x, double* out) {
+  if (method == ORC_RK4) {
+    orc_rk4_step(sys, d, P, h, x, out);
+    return 0;
+  }
+  return orc_integrate_implicit(method, sys, d, P, h, 1, x, out);
+}
+
+/*
+ * Parareal (Sec. 2.2, eqs. parareal-init, fine-integrator,
+ * coarse-integrator) over M windows of S fine steps each:
+ *   coarse G(x) = one step of the rule with step size S*dt,
+ *   fine   F(x) = S steps of the rule with step size dt.
+ * Initial coarse sweep x_{m+1} = G(x_m), x_0 = x0; then per iteration
+ *   F_m = F(x_m) for every window (independent of each other),
+ *   R = max_m ||x_{m+1} - F_m||_inf (the paper's error measure R^(k)),
+ *   stop if R < tol (strict), else the sequential correction
+ *   x_{m+1} <- G(x_m new) + F_m - G(x_m old).
+ * The paper takes M = floor(sqrt(N)) and S = floor(N / M) (a reading: with
+ * them this function reproduces the paper's printed R histories).
+ *
+ * traj ([M*S][d]) receives the dense trajectory of the last fine sweep:
+ * traj[m*S + j] is the state after j+1 fine steps of window m.  hist
+ * (length >= max_iter, may be NULL) receives R of each fine sweep.  *iters
+ * receives K, the number of fine sweeps (= residual evaluations, the count
+ * the paper plots); *final_resid the last R.  Returns ORC_OK,
+ * ORC_NOT_CONVERGED (max_iter sweeps without R < tol) or ORC_NONFINITE (a
+ * non-finite R or an implicit step that did not converge).
+ */
+int orc_parareal(int method, int sys, int d, const double* P, double dt, int64_t M,
+                 int64_t S, const double* x0, double tol, int64_t max_iter,
+                 double* traj, double* hist, int64_t* iters, double* final_resid) {
+  size_t sd = (size_t)d;
+  int status = ORC_OK;
+  int64_t k = 0;
+  double R = 0.0;
+  if (M <= 0 || S <= 0) {
+    if (iters) *iters = 0;
+    if (final_resid) *final_resid = 0.0;
+    return ORC_OK;
+  }
+  double H = (double)S * dt;
+  double* x = (double*)malloc(sizeof(double) * (size_t)(M + 1) * sd);    /* x_0..x_M   */
+  double* xn = (double*)malloc(sizeof(double) * (size_t)(M + 1) * sd);   /* next iterate */
+  double* F = (double*)malloc(sizeof(double) * (size_t)M * sd);          /* F_m        */
+  double* Gold = (double*)malloc(sizeof(double) * (size_t)M * sd);       /* G(x_m) old */
+  double* Gnew = (double*)malloc(sizeof(double) * sd);
+
+  /* eq. parareal-init */
+  memcpy(x, x0, sizeof(double) * sd);
+  for (int64_t m = 0; m < M && status == ORC_OK; m++) {
+    if (one_step(method, sys, d, P, H, x + (size_t)m * sd, Gold + (size_t)m * sd) != 0)
+      status = ORC_NONFINITE;
+    memcpy(x + (size_t)(m + 1) * sd, Gold + (size_t)m * sd, sizeof(double) * sd);
+  }
+  while (status == ORC_OK) {
+    /* eq. fine-integrator: every window from its own start */
+    for (int64_t m = 0; m < M && status == ORC_OK; m++) {
+      const double* prev = x + (size_t)m * sd;
+      for (int64_t j = 0; j < S; j++) {
+        double* cur = traj + (size_t)(m * S + j) * sd;
+        if (one_step(method, sys, d, P, dt, prev, cur) != 0) { status = ORC_NONFINITE; break; }
+        prev = cur;
+      }
+      memcpy(F + (size_t)m * sd, prev, sizeof(double) * sd);
+    }
+    if (status != ORC_OK) break;
+    /* R = max over windows of |x_{m+1} - F_m| */
+    R = 0.0;
+    for (int64_t m = 0; m < M; m++)
+      for (size_t i = 0; i < sd; i++) {
+        double e = x[(size_t)(m + 1) * sd + i] - F[(size_t)m * sd + i];
+        if (!isfinite(e)) R = INFINITY;
+        else if (fabs(e) > R) R = fabs(e);
+      }
+    if (hist) hist[k] = R;
+    k++;
+    if (!isfinite(R)) { status = ORC_NONFINITE; break; }
+    if (R < tol) break;
+    if (k >= max_iter) { status = ORC_NOT_CONVERGED; break; }
+    /* eq. coarse-integrator: sequential correction sweep */
+    memcpy(xn, x0, sizeof(double) * sd);
+    for (int64_t m = 0; m < M; m++) {
+      if (one_step(method, sys, d, P, H, xn + (size_t)m * sd, Gnew) != 0) {
+        status = ORC_NONFINITE;
+        break;
+      }
+      for (size_t i = 0; i < sd; i++)
+        xn[(size_t)(m + 1) * sd + i] = (Gnew[i] + F[(size_t)m * sd + i]) - Gold[(size_t)m * sd + i];
+      memcpy(Gold + (size_t)m * sd, Gnew, sizeof(double) * sd);
+    }
+    double* t = x; x = xn; xn = t;
+  }
+  if (iters) *iters = k;
+  if (final_resid) *final_resid = R;
+  free(x);
+  free(xn);
+  free(F);
+  free(Gold);
+  free(Gnew);
+  return status;
+}
