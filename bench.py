@@ -231,6 +231,53 @@ def leg_paper_runtime(P, torch, dev, stream, reps=2):
     return out
 
 
+# The paper's Parareal A100 times (JAX, Figures 4 and 7) at the largest T of
+# each PAPER_RUNTIME problem, in seconds: context only.
+PAPER_PARAREAL_A100 = {"logistic": 0.05735576, "vdp": 0.53979595, "cartpole": 0.06637533,
+                       "dahlquist": 0.22486305, "robertson": 1.46933091}
+
+
+def leg_parareal(P, torch, dev, stream, reps=2, tol=3e-14):
+    """Parareal (Sec. 2.2; M = floor(sqrt(N)) windows of floor(N/M) fine
+    steps, one coarse step per window) against the Newton solve and the
+    sequential integrator of the same rule, at the largest T of each of the
+    paper's runtime problems and the same tolerance for both methods."""
+    out = {}
+    for name, sysid, method, prm, x0l, gval, horizon, Ts, paper in PAPER_RUNTIME:
+        T = Ts[-1]
+        dt = horizon / T
+        M, S = P.parareal_windows(T)
+        x0 = torch.tensor(x0l, dtype=torch.float64, device=dev)
+        pr = torch.tensor(prm, dtype=torch.float64, device=dev)
+        res = {}
+
+        def run_pr():
+            res["p"] = P.parareal(sysid, x0, pr, dt, M, S, tol=tol, max_iter=60, method=method,
+                                  stream=stream)
+
+        ms_pr = _time(run_pr, reps, stream)
+        _, k_pr, r_pr, st_pr = res["p"]
+        guess = torch.full((T, len(x0l)), gval, dtype=torch.float64, device=dev)
+
+        def run_nt():
+            res["n"] = P.solve(sysid, x0, pr, dt, T, tol=tol, max_iter=60, guess=guess,
+                               method=method, stream=stream)
+
+        ms_nt = _time(run_nt, reps, stream)
+        _, it_nt, _, st_nt = res["n"]
+        ms_seq = _time(lambda: P.seq_integrate(sysid, x0[None], pr, dt, T, method=method,
+                                               stream=stream), 1, stream)
+        out[name] = {"T": T, "M": M, "S": S, "tol": tol,
+                     "parareal_ms": ms_pr, "parareal_K": int(k_pr), "parareal_status": int(st_pr),
+                     "parareal_R": float(r_pr),
+                     "newton_ms": ms_nt, "newton_K": int(it_nt) + 1, "newton_status": int(st_nt),
+                     "sequential_ms": ms_seq,
+                     "newton_speedup_over_parareal": ms_pr / ms_nt,
+                     "paper_a100_context_ms": {"parareal": PAPER_PARAREAL_A100[name] * 1e3,
+                                               "newton": paper[1] * 1e3}}
+    return out
+
+
 def leg_robertson_batch(P, torch, dev, stream, reps=3):
     """1024 Robertson instances (rates scattered around the paper's, T ~
     U{1000..5000}), backward Euler, dt = 0.1, plain Newton at tol 1e-10,
@@ -327,7 +374,7 @@ def main():
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and comparator legs")
-    ap.add_argument("--legs", default="scan,dense,vdp,adjoint,kuramoto,paper,implicit",
+    ap.add_argument("--legs", default="scan,dense,vdp,adjoint,kuramoto,parareal,implicit",
                     help="extra workloads to measure (comma list, or 'none')")
     args = ap.parse_args()
 
@@ -474,6 +521,8 @@ def main():
             extra["paper_runtime"] = leg_paper_runtime(P, torch, dev, stream)
         elif leg == "implicit":
             extra["robertson_batch"] = leg_robertson_batch(P, torch, dev, stream)
+        elif leg == "parareal":
+            extra["parareal"] = leg_parareal(P, torch, dev, stream)
         print(f"[bench] leg {leg} done", file=sys.stderr, flush=True)
 
     flops = lorenz96_step_flops(d, args.window)

@@ -238,6 +238,42 @@ pint_status pint_seq_integrate(const pint_system* sys, int64_t B,
                                int64_t T_max, int32_t dtype, void* traj,
                                pint_stream_t stream);
 
+/*
+ * pint_parareal — Parareal, the method the paper compares against (Sec. 2.2,
+ * eqs. parareal-init, fine-integrator, coarse-integrator), for B
+ * independent instances split the same way: M windows of S fine steps.  The
+ * coarse integrator G is ONE step of sys->method with step size S*dt; the
+ * fine integrator F is S steps of size dt.  Initial coarse sweep
+ * x_{m+1} = G(x_m) from x_0 = x0; then per iteration the fine sweep
+ * F_m = F(x_m) over all windows in parallel, the error
+ * R = max_m ||x_{m+1} - F_m||_inf (the paper's R^(k), Sec. 4), a stop when
+ * R < opts->tol (strict), else the sequential correction
+ * x_{m+1} <- G(x_m new) + F_m - G(x_m old).  The paper takes
+ * M = floor(sqrt(N)) and S = floor(N / M) for N steps (the caller chooses).
+ *   x0      [B][d]
+ *   traj    [B][M*S][d]   out: the dense trajectory of the last fine sweep
+ *                         (traj[b][m*S + j] = state after j+1 fine steps of
+ *                         window m)
+ *   iters   [B] int64     K, the number of fine sweeps (= R evaluations)
+ *   resid   [B] double    the last R
+ *   status  [B] int32     PINT_OK, PINT_NOT_CONVERGED (max_iter sweeps), or
+ *                         PINT_NONFINITE (a non-finite R)
+ *   hist    [B][max_iter] double, R of each sweep (entries past K are not
+ *                         written), or NULL
+ * opts: dtype, tol, max_iter (fine sweeps; <= 0 means M + 1, after which
+ * Parareal is exact); every other field must be 0 / NULL (guard is
+ * ignored).  Systems of dimension d <= 4 only (PINT_ERR_UNSUPPORTED
+ * otherwise).  One workgroup per instance; workspace from
+ * pint_parareal_workspace_bytes ((3M + 1) states per instance).  M or S = 0
+ * gives K = 0, R = 0, PINT_OK and writes no trajectory.
+ */
+size_t pint_parareal_workspace_bytes(const pint_system* sys, int64_t B, int64_t M,
+                                     int32_t dtype);
+pint_status pint_parareal(const pint_system* sys, int64_t B, const void* x0, double dt,
+                          int64_t M, int64_t S, const pint_options* opts, void* traj,
+                          int64_t* iters, double* resid, int32_t* status, double* hist,
+                          void* ws, size_t ws_bytes, pint_stream_t stream);
+
 /* pint_residual — h_n = x_n - Phi(x_{n-1}) for every step of a uniform
  * batch (eq. root-finding-problem; the scaled implicit residual of
  * pint_method for the implicit rules): h [B][T][d] (may be NULL), and

@@ -60,7 +60,8 @@ EXPORTS = ["pint_n_params", "pint_status_string", "pint_supported", "pint_worksp
            "pint_elements", "pint_scan_workspace_bytes", "pint_affine_scan",
            "pint_scan_band_workspace_bytes", "pint_affine_scan_band",
            "pint_adjoint_workspace_bytes", "pint_adjoint", "pint_graph_capture_varlen",
-           "pint_graph_launch", "pint_graph_destroy", "pint_set_wait_limit"]
+           "pint_graph_launch", "pint_graph_destroy", "pint_set_wait_limit",
+           "pint_parareal_workspace_bytes", "pint_parareal"]
 
 # include/pint.h: PINT_WAIT_LIMIT_DEFAULT
 WAIT_LIMIT_DEFAULT = 268435456
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH):
         "pint_graph_launch": (C.c_int, [vp, vp]),
         "pint_graph_destroy": (C.c_int, [vp]),
         "pint_set_wait_limit": (None, [C.c_uint64]),
+        "pint_parareal_workspace_bytes": (sz, [SP, i64, i64, i32]),
+        "pint_parareal": (C.c_int, [SP, i64, vp, dbl, i64, i64, OP, vp, vp, vp, vp, vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -270,6 +273,17 @@ def pint_set_wait_limit(polls: int) -> None:
     load().pint_set_wait_limit(int(polls))
 
 
+def pint_parareal_workspace_bytes(sysd, B, M, dtype) -> int:
+    return load().pint_parareal_workspace_bytes(C.byref(sysd), B, M, dtype)
+
+
+def pint_parareal(sysd, B, x0, dt, M, S, opts, traj, iters, resid, status, hist, ws,
+                  stream=None) -> int:
+    return load().pint_parareal(C.byref(sysd), B, _ptr(x0), dt, M, S, C.byref(opts), _ptr(traj),
+                                _ptr(iters), _ptr(resid), _ptr(status), _ptr(hist), _ptr(ws),
+                                0 if ws is None else ws.numel(), _stream(stream))
+
+
 # ---------------------------------------------------------- conveniences --
 
 def _workspace(nbytes: int, device) -> Optional[torch.Tensor]:
@@ -307,6 +321,48 @@ def solve(system, x0: torch.Tensor, params: torch.Tensor, dt: float, T: int, *,
     if single:
         return traj[0], iters[0], resid[0], status[0]
     return traj, iters, resid, status
+
+
+def parareal_windows(N: int):
+    """The paper's split of N steps (Sec. 4.1): M = floor(sqrt(N)) windows
+    of S = floor(N / M) fine steps."""
+    import math
+    M = math.isqrt(int(N))
+    return (M, int(N) // M) if M > 0 else (0, 0)
+
+
+def parareal(system, x0: torch.Tensor, params: torch.Tensor, dt: float, M: int, S: int, *,
+             tol: float = 1e-10, max_iter: int = 0, method=RK4, with_hist: bool = False,
+             stream=None):
+    """Parareal of a uniform batch (pint_parareal).  x0 [B, d] (or [d]);
+    params [n_params] or [B, n_params].  Returns (traj [B, M*S, d], iters
+    [B] int64 (fine sweeps K), resid [B] float64 (last R), status [B] int32)
+    and, with with_hist, hist [B, max_iter] float64 (NaN past K)."""
+    sid = _sys_id(system)
+    single = x0.dim() == 1
+    x0 = (x0[None] if single else x0).contiguous()
+    B, d = x0.shape
+    M, S = int(M), int(S)
+    prm, shared = _params_2d(params.to(x0.dtype), B, n_params(sid, d))
+    dt_code = _dtype_code(x0)
+    dev = x0.device
+    traj = torch.empty((B, M * S, d), dtype=x0.dtype, device=dev)
+    iters = torch.empty(B, dtype=torch.int64, device=dev)
+    resid = torch.empty(B, dtype=torch.float64, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    kmax = int(max_iter) if max_iter > 0 else M + 1
+    hist = torch.full((B, kmax), float("nan"), dtype=torch.float64, device=dev) if with_hist else None
+    sysd = make_system(sid, d, prm, shared, method)
+    opts = make_options(dt_code, tol, 0, kmax)
+    ws = _workspace(pint_parareal_workspace_bytes(sysd, B, M, dt_code), dev)
+    _check(pint_parareal(sysd, B, x0, float(dt), M, S, opts, traj, iters, resid, status, hist, ws,
+                         stream), "pint_parareal")
+    out = (traj, iters, resid, status)
+    if single:
+        out = tuple(t[0] for t in out)
+    if with_hist:
+        out = out + ((hist[0] if single else hist),)
+    return out
 
 
 def longest_first(lengths, device) -> torch.Tensor:

@@ -250,6 +250,34 @@ pint_status pint_seq_integrate(const pint_system* sys, int64_t B, const void* x0
   return (pint_status)rc;
 }
 
+size_t pint_parareal_workspace_bytes(const pint_system* sys, int64_t B, int64_t M, int32_t dtype) {
+  if (!sys || B < 0 || M < 0 || (dtype != PINT_F64 && dtype != PINT_F32)) return 0;
+  return parareal_ws_bytes(sys->d, B, M, dtype);
+}
+
+pint_status pint_parareal(const pint_system* sys, int64_t B, const void* x0, double dt, int64_t M,
+                          int64_t S, const pint_options* opts, void* traj, int64_t* iters,
+                          double* resid, int32_t* status, double* hist, void* ws, size_t ws_bytes,
+                          pint_stream_t stream) {
+  if (int rc = check_sys(sys, B)) return (pint_status)rc;
+  if (!is_small(sys->system, sys->d)) return PINT_ERR_UNSUPPORTED;
+  if (!opts || (opts->dtype != PINT_F64 && opts->dtype != PINT_F32) || !(opts->tol > 0.0))
+    return PINT_ERR_INVALID_ARG;
+  if (opts->guess != 0 || opts->window != 0 || opts->tile != 0 || opts->flags != 0 ||
+      opts->block != 0 || opts->wg_per_cu != 0 || opts->order)
+    return PINT_ERR_INVALID_ARG;
+  if (!std::isfinite(dt) || M < 0 || S < 0) return PINT_ERR_INVALID_ARG;
+  if (M > 0 && S > INT64_MAX / M) return PINT_ERR_INVALID_ARG;
+  if (B > 2147483647) return PINT_ERR_INVALID_ARG;  // one workgroup per instance
+  if (B == 0) return PINT_OK;
+  if (!x0 || !iters || !resid || !status || (M > 0 && S > 0 && !traj)) return PINT_ERR_INVALID_ARG;
+  const int64_t max_iter = opts->max_iter > 0 ? opts->max_iter : M + 1;
+  SolveArgs a = make_args(sys, B, x0, dt, nullptr, M * S, M * S, opts, traj, iters, resid, status,
+                          ws, ws_bytes, stream);
+  a.max_iter = max_iter;
+  return (pint_status)parareal(a, M, S, hist);
+}
+
 pint_status pint_residual(const pint_system* sys, int64_t B, const void* x0, double dt, int64_t T,
                           int32_t dtype, const void* traj, void* h, double* hmax,
                           pint_stream_t stream) {

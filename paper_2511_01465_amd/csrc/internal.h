@@ -65,6 +65,10 @@ int affine_scan_band(int d, int bw, int boff, int64_t B, int64_t N, int dtype, c
 size_t adjoint_ws_bytes(int system, int d, int64_t B, int64_t T, int64_t seg, int dtype);
 int adjoint(const SolveArgs& a, const void* g, void* dL_dx0, void* dL_dth, int64_t seg);
 
+// Parareal (parareal.hip): M windows of S fine steps; hist [B][max_iter] or nullptr.
+size_t parareal_ws_bytes(int d, int64_t B, int64_t M, int dtype);
+int parareal(const SolveArgs& a, int64_t M, int64_t S, double* hist);
+
 // Polls before a cross-workgroup wait of the cooperative solvers gives up
 // (process-wide; set through pint_set_wait_limit).
 uint64_t wait_limit();

@@ -350,6 +350,10 @@ struct StepRule<T, S, METHOD_RK4> {
     for (int i = 0; i < D; i++) b[i] = phi[i] - xc[i];
   }
   __device__ static void advance(const T* P, T dt, const T* xp, T* xn) { rk4_phi<T, S>(P, dt, xp, xn); }
+  __device__ static bool advance_ok(const T* P, T dt, const T* xp, T* xn) {
+    rk4_phi<T, S>(P, dt, xp, xn);
+    return true;
+  }
 };
 
 // Implicit rules x_n = x_{n-1} + g(x_{n-1}, x_n) (Sec. 3.4, eq. implicit-ode):
@@ -421,8 +425,10 @@ struct StepRule {
   }
   // Sequential step: Newton's method on x_n - xp - g(xp, x_n) = 0 from
   // x_n = xp, until the correction is within a few ulps of |x_n| (at most
-  // 100 corrections).
-  __device__ static void advance(const T* P, T dt, const T* xp, T* xn) {
+  // 100 corrections).  advance_ok returns false when the 100 corrections
+  // did not get there (a non-finite correction also ends the loop, as
+  // converged: the non-finite state reports itself downstream).
+  __device__ static bool advance_ok(const T* P, T dt, const T* xp, T* xn) {
     const T stop = sizeof(T) == 8 ? T(4 * 2.220446049250313e-16) : T(32 * 1.1920929e-7);
 #pragma unroll
     for (int i = 0; i < D; i++) xn[i] = xp[i];
@@ -437,8 +443,12 @@ struct StepRule {
         dn = fmax(dn, fabs(h[i]));
         yn = fmax(yn, fabs(xn[i]));
       }
-      if (!(dn > stop * yn)) break;  // also ends on a non-finite correction
+      if (!(dn > stop * yn)) return true;
     }
+    return false;
+  }
+  __device__ static void advance(const T* P, T dt, const T* xp, T* xn) {
+    (void)advance_ok(P, dt, xp, xn);
   }
 };
 

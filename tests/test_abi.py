@@ -153,3 +153,32 @@ def test_affine_scan_argument_checks():
     assert need > 0
     assert scan(3, 1, 16, P.F64, fake, fake, fake, 0, None, need) == P.ERR_WORKSPACE
     assert scan(3, 1, 16, P.F64, fake, fake, fake, 0, fake, need - 1) == P.ERR_WORKSPACE
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpint.so not built")
+def test_parareal_argument_checks():
+    """pint_parareal's error returns, each decided before any HIP call (the
+    pointers below are never dereferenced)."""
+    import paper_2511_01465_amd as P
+    lib = P.load()
+    fake = ctypes.c_void_p(256)
+    vdp = P.pint_system(P.VDP, 2, 1, 1, fake)
+    opts = P.make_options(P.F64, 1e-10)
+
+    def call(sysd, B, M, S, o, ws=None, nbytes=0, x0=fake):
+        return lib.pint_parareal(ctypes.byref(sysd), B, x0, 1e-2, M, S, ctypes.byref(o), fake,
+                                 fake, fake, fake, None, ws, nbytes, None)
+
+    assert call(vdp, 0, 4, 4, opts) == P.OK                                  # empty batch
+    assert call(vdp, 1, -1, 4, opts) == P.ERR_INVALID_ARG
+    assert call(vdp, 1, 4, -1, opts) == P.ERR_INVALID_ARG
+    assert call(vdp, 1, 4, 4, P.make_options(P.F64, 0.0)) == P.ERR_INVALID_ARG   # tol must be > 0
+    assert call(vdp, 1, 4, 4, P.make_options(P.F64, 1e-10, window=4)) == P.ERR_INVALID_ARG
+    assert call(vdp, 1, 4, 4, P.make_options(7, 1e-10)) == P.ERR_INVALID_ARG
+    assert call(vdp, 1, 4, 4, opts, x0=None) == P.ERR_INVALID_ARG
+    l96 = P.pint_system(P.LORENZ96, 40, 1, 1, fake)
+    assert call(l96, 1, 4, 4, opts) == P.ERR_UNSUPPORTED                     # small d only
+    need = lib.pint_parareal_workspace_bytes(ctypes.byref(vdp), 1, 4, P.F64)
+    assert need >= 13 * 2 * 8                                              # (3M + 1) states
+    assert call(vdp, 1, 4, 4, opts, None, need) == P.ERR_WORKSPACE
+    assert call(vdp, 1, 4, 4, opts, fake, need - 1) == P.ERR_WORKSPACE
