@@ -313,6 +313,33 @@ pint_status pint_affine_scan(int32_t d, int64_t B, int64_t N, int32_t dtype,
                              void* z, int32_t tile, void* ws, size_t ws_bytes,
                              pint_stream_t stream);
 
+/*
+ * pint_affine_scan_noalloc — pint_affine_scan for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, recursion, outputs and
+ * argument checks as pint_affine_scan, without the workspace: the scan's
+ * scratch (tile counter, error word, tile flags and payloads, as sized by
+ * pint_scan_workspace_bytes) is a fixed device array of
+ * PINT_NOALLOC_SCRATCH_BYTES inside the library, one per device, reserved
+ * when the library's code is loaded on the device and held until the
+ * process ends.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library call); its first call on a device looks up that
+ * device's array address.
+ *   err  device uint32, or NULL: receives 0, or 1 if a lookback wait gave up
+ *        (the bounded wait of the scan; the result is then unreliable).
+ * Returns PINT_ERR_WORKSPACE, before launching anything, when
+ * pint_scan_workspace_bytes for these sizes exceeds
+ * PINT_NOALLOC_SCRATCH_BYTES (e.g. d = 128 over more than ~120 tiles).
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (other streams, other host threads) race and give wrong
+ * results.  Calls ordered on one stream are safe: each call first clears
+ * what must start at zero, so what an earlier call left there is harmless.
+ */
+#define PINT_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+pint_status pint_affine_scan_noalloc(int32_t d, int64_t B, int64_t N, int32_t dtype,
+                                     const void* A, const void* b, const void* z0, void* z,
+                                     int32_t tile, uint32_t* err, pint_stream_t stream);
+
 /* pint_affine_scan_band — pint_affine_scan for elements whose A is
  * cyclically banded: A_n(i, (i + k - boff) mod d) = band_n[i][k] for
  * k < bw, every other entry exactly zero (the RK4 Jacobian of a

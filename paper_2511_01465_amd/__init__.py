@@ -61,7 +61,7 @@ EXPORTS = ["pint_n_params", "pint_status_string", "pint_supported", "pint_worksp
            "pint_scan_band_workspace_bytes", "pint_affine_scan_band",
            "pint_adjoint_workspace_bytes", "pint_adjoint", "pint_graph_capture_varlen",
            "pint_graph_launch", "pint_graph_destroy", "pint_set_wait_limit",
-           "pint_parareal_workspace_bytes", "pint_parareal"]
+           "pint_parareal_workspace_bytes", "pint_parareal", "pint_affine_scan_noalloc"]
 
 # include/pint.h: PINT_WAIT_LIMIT_DEFAULT
 WAIT_LIMIT_DEFAULT = 268435456
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "pint_graph_destroy": (C.c_int, [vp]),
         "pint_set_wait_limit": (None, [C.c_uint64]),
         "pint_parareal_workspace_bytes": (sz, [SP, i64, i64, i32]),
+        "pint_affine_scan_noalloc": (C.c_int, [i32, i64, i64, i32, vp, vp, vp, vp, i32, vp, vp]),
         "pint_parareal": (C.c_int, [SP, i64, vp, dbl, i64, i64, OP, vp, vp, vp, vp, vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
@@ -227,6 +228,15 @@ def pint_scan_workspace_bytes(d, B, N, tile, dtype) -> int:
 def pint_affine_scan(d, B, N, dtype, A, b, z0, z, tile, ws, stream=None) -> int:
     return load().pint_affine_scan(d, B, N, dtype, _ptr(A), _ptr(b), _ptr(z0), _ptr(z), tile,
                                    _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream))
+
+
+def pint_affine_scan_noalloc(d, B, N, dtype, A, b, z0, z, tile, err=None, stream=None) -> int:
+    return load().pint_affine_scan_noalloc(d, B, N, dtype, _ptr(A), _ptr(b), _ptr(z0), _ptr(z),
+                                           tile, _ptr(err), _stream(stream))
+
+
+# include/pint.h: PINT_NOALLOC_SCRATCH_BYTES
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 def pint_scan_band_workspace_bytes(d, bw, boff, B, N, tile, dtype) -> int:

@@ -325,6 +325,17 @@ pint_status pint_affine_scan(int32_t d, int64_t B, int64_t N, int32_t dtype, con
                                   reinterpret_cast<hipStream_t>(stream));
 }
 
+pint_status pint_affine_scan_noalloc(int32_t d, int64_t B, int64_t N, int32_t dtype,
+                                     const void* A, const void* b, const void* z0, void* z,
+                                     int32_t tile, uint32_t* err, pint_stream_t stream) {
+  if (d < 1 || B < 0 || N < 0 || tile < 0 || (dtype != PINT_F64 && dtype != PINT_F32))
+    return PINT_ERR_INVALID_ARG;
+  if (B == 0 || N == 0) return PINT_OK;
+  if (!A || !b || !z) return PINT_ERR_INVALID_ARG;
+  return (pint_status)affine_scan_noalloc(d, B, N, dtype, A, b, z0, z, tile, err,
+                                          reinterpret_cast<hipStream_t>(stream));
+}
+
 size_t pint_scan_band_workspace_bytes(int32_t d, int32_t bw, int32_t boff, int64_t B, int64_t N,
                                       int32_t tile, int32_t dtype) {
   if (dtype != PINT_F64 && dtype != PINT_F32) return 0;

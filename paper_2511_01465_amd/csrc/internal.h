@@ -57,6 +57,10 @@ size_t scan_ws_bytes(int d, int64_t B, int64_t N, int tile, int dtype);
 int affine_scan(int d, int64_t B, int64_t N, int dtype, const void* A, const void* b,
                 const void* z0, void* z, int tile, void* ws, size_t ws_bytes, hipStream_t s);
 
+// pint_affine_scan with the library's fixed device scratch (scan.hip).
+int affine_scan_noalloc(int d, int64_t B, int64_t N, int dtype, const void* A, const void* b,
+                        const void* z0, void* z, int tile, uint32_t* err_out, hipStream_t s);
+
 size_t scan_band_ws_bytes(int d, int bw, int boff, int64_t B, int64_t N, int tile, int dtype);
 int affine_scan_band(int d, int bw, int boff, int64_t B, int64_t N, int dtype, const void* band,
                      const void* b, const void* z0, void* z, int tile, void* ws, size_t ws_bytes,

@@ -26,6 +26,9 @@
 //     from global memory, scan and lookback through LDS;
 //   dense d (16..128): each tile folds its elements with MFMA matrix
 //     products (FP64 16x16x4 or FP32 16x16x4), the running product in LDS.
+#include <mutex>
+
+#include "../../include/pint.h"
 #include "internal.h"
 #include "device_common.h"
 
@@ -1649,6 +1652,62 @@ int affine_scan_band(int d, int bw, int boff, int64_t B, int64_t N, int dtype, c
   if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w), 64 + (size_t)nt, 0u, s)) return rc;
   if (boff == 4) return dtype == 0 ? launch_band<double, 4>(sa, nt, s) : launch_band<float, 4>(sa, nt, s);
   return dtype == 0 ? launch_band<double, 8>(sa, nt, s) : launch_band<float, 8>(sa, nt, s);
+}
+
+// ------------------------------------------- fixed-scratch scan variant --
+
+// The scratch of pint_affine_scan_noalloc: a file-scope device array in place
+// of a caller workspace, one copy per device, reserved when the library's code
+// object is loaded on that device and held until the process ends.  In host
+// code `scratch` names a host-side stand-in, not device memory: its device
+// address is looked up once per device with hipGetSymbolAddress (that device
+// current) and only that address is ever passed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = PINT_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+static int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return ST_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ST_DEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ST_OK;
+}
+
+__global__ void k_copy_word(const uint32_t* src, uint32_t* dst) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    *dst = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+int affine_scan_noalloc(int d, int64_t B, int64_t N, int dtype, const void* A, const void* b,
+                        const void* z0, void* z, int tile, uint32_t* err_out, hipStream_t s) {
+  if (d > 8 && !scan_dense_d(d)) return ST_UNSUPPORTED;
+  if (dtype != 0 && dtype != 1) return ST_INVALID;
+  const size_t need = scan_ws_bytes(d, B, N, tile, dtype);
+  if (need == 0) return ST_INVALID;
+  if (need > NOALLOC_SCRATCH_BYTES) return ST_WORKSPACE;
+  void* p = nullptr;
+  if (int rc = scratch_address(&p)) return rc;
+  // affine_scan clears the tile counter, the error word and the flags it
+  // uses with a fill kernel first, so what an earlier call left is harmless
+  if (int rc = affine_scan(d, B, N, dtype, A, b, z0, z, tile, p, NOALLOC_SCRATCH_BYTES, s))
+    return rc;
+  if (err_out) {  // the error word sits at byte offset 4 of the scratch
+    hipLaunchKernelGGL(k_copy_word, dim3(1), dim3(64), 0, s,
+                       static_cast<const uint32_t*>(p) + 1, err_out);
+    if (hipGetLastError() != hipSuccess) return ST_DEVICE;
+  }
+  return ST_OK;
 }
 
 }  // namespace pint
