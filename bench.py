@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6e12   # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_HBM = 8.0e12
+PEAK_FP32_MFMA = 157.3e12  # MI355X dense FP32 matrix
 
 
 def lorenz96_step_flops(d: int, window: int) -> dict:
@@ -62,6 +63,45 @@ def measured_traffic(kernel: str, T: int, window: int):
     return int(rec["read_bytes"] + rec["write_bytes"]), (
         "profiles/hbm_traffic_pmc.md: read %.3f GB + written %.3f GB" % (rec["read_bytes"] / 1e9,
                                                                            rec["write_bytes"] / 1e9))
+
+
+# ------------------------------------------------------------ helpers ----
+
+CURVE_STEPS = (1, 2, 5, 10, 20, 50, 100, 200, 500, 1000, 2000, 5000, 10000, 20000, 50000)
+
+
+def err_curve(got, ref, bar=1e-4):
+    """Per-step error of a trajectory [T, d] against an FP64 reference:
+    max_i |got - ref| / max(1, max_i |ref|) at log-spaced steps n (1-based),
+    and the first step where it exceeds `bar`."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    T = min(len(got), len(ref))
+    scale = np.maximum(1.0, np.abs(ref[:T]).max(axis=1))
+    e = np.abs(got[:T] - ref[:T]).max(axis=1) / scale
+    e = np.where(np.isfinite(e), e, np.inf)
+    steps = [n for n in CURVE_STEPS if n <= T] + ([T] if T not in CURVE_STEPS else [])
+    over = np.nonzero(e > bar)[0]
+    return {"steps": steps, "rel_err": [float(e[n - 1]) for n in steps],
+            "first_step_above_%g" % bar: int(over[0]) + 1 if len(over) else None}
+
+
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = os.cpu_count() or 1
+    try:
+        n_aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n_aff = n
+    return {"model": model, "nproc": n, "usable_cores": n_aff}
 
 
 # ------------------------------------------------------------ extra legs --
@@ -137,9 +177,27 @@ def leg_dense_fullT(P, torch, dev, stream, which, reps=3):
            "scan_TFLOPs": fl / (ms_sc / 1e3) / 1e12, "scan_frac_fp64_mfma": fl / (ms_sc / 1e3) / PEAK_FP64_VALU,
            "elements_GB/s_written": n * (d * d + d) * 8 / (ms_el / 1e3) / 1e9,
            "converged_steps_per_s_if_one_iteration": n / ((ms_el + ms_sc) / 1e3)}
-    del A, b, z, ws, traj
+    # kept for the oracle check of the CPU leg: at the constant iterate every
+    # element of an instance is the same (A = dPhi/dx(x0), b = Phi(x0) - x0),
+    # so the oracle's recursion from its own A and b is the scan's exact
+    # output (Lorenz-96: the first 2048 elements, before the chaotic products
+    # leave the FP64 range)
+    ncheck = T if which == "kuramoto" else 2048
+    samples = {"workload": w, "ncheck": ncheck,
+               "fp64": {i: z[i, :ncheck].cpu().numpy() for i in (0, B - 1)}}
+    # FP32 variant: the same elements rounded, scanned on FP32 MFMA
+    A32, b32 = A.float(), b.float()
+    del A
+    z32 = torch.empty((B, T, d), dtype=torch.float32, device=dev)
+    ws32 = torch.empty(P.pint_scan_workspace_bytes(d, B, T, 0, P.F32), dtype=torch.uint8, device=dev)
+    ms32 = _time(lambda: P.pint_affine_scan(d, B, T, P.F32, A32, b32, None, z32, 0, ws32, stream),
+                 reps, stream)
+    res["fp32"] = {"scan_ms": ms32, "scan_TFLOPs": fl / (ms32 / 1e3) / 1e12,
+                   "scan_frac_fp32_mfma": fl / (ms32 / 1e3) / PEAK_FP32_MFMA}
+    samples["fp32"] = {0: z32[0, :ncheck].double().cpu().numpy()}
+    del A32, b32, z32, ws32, b, z, ws, traj
     torch.cuda.empty_cache()
-    return res
+    return res, samples
 
 
 def leg_vdp_batch(P, torch, dev, stream, reps=3, window=256):
@@ -169,7 +227,15 @@ def leg_vdp_batch(P, torch, dev, stream, reps=3, window=256):
     ms = _time(lambda: g.launch(stream), reps, stream)
     iters, resid, status = g.iters, g.resid, g.status
     ms_seq = _time(lambda: P.seq_integrate(P.VDP, x0, prm, w.dt, lengths), reps, stream)
+    # algorithmic HBM bytes of the windowed solve: every update reads the
+    # window's states and writes them back, 2 d 8 bytes per window step
+    it_h = iters.cpu().numpy().astype(np.float64)
+    win = np.minimum(cfg["window"], w.T).astype(np.float64)
+    hbm_bytes = float((it_h * win).sum()) * 2 * w.d * 8
     out = {"instances": w.B, "sum_T": total, "ms": ms, "value": total / (ms / 1e3),
+           "hbm": {"algorithmic_bytes": hbm_bytes, "GB/s": hbm_bytes / (ms / 1e3) / 1e9,
+                   "frac_hbm": hbm_bytes / (ms / 1e3) / PEAK_HBM,
+                   "per_unit": "2 d 8 bytes per window step per update"},
            "launch": "hip graph", "tuned": {k: cfg[k] for k in ("window", "block", "wg_per_cu", "order")},
            "tuning_trials": len(cfg["trials"]),
            "all_ok": bool((status == 0).all()), "max_resid": float(resid.max()),
@@ -342,6 +408,10 @@ def leg_adjoint(P, torch, dev, stream, B=256, T=16384, window=0, seg=2048, reps=
 
 
 def leg_kuramoto(P, torch, dev, stream, window=256, reps=2):
+    """Kuramoto d=128, 8 x 4096, windowed Newton W=256 in FP64, and the same
+    solve in FP32 (tol 16 eps_32 max(1, ||xi||_inf)); the sequential
+    integrator beside it.  The FP32 trajectories are kept for the CPU leg's
+    per-step error against the FP64 oracle."""
     import workloads as W
     w = W.kuramoto(window=window)
     x0 = torch.tensor(w.x0, device=dev)
@@ -354,11 +424,147 @@ def leg_kuramoto(P, torch, dev, stream, window=256, reps=2):
 
     ms = _time(run, reps, stream)
     traj, iters, resid, status = res["o"]
-    T_off = torch.arange(0, (w.B + 1) * T, T, dtype=torch.int64)
     ms_seq = _time(lambda: P.seq_integrate(P.KURAMOTO, x0, prm, w.dt, T), reps, stream)
-    return {"instances": w.B, "T": T, "window": window, "ms": ms, "value": w.B * T / (ms / 1e3),
-            "all_ok": bool((status == 0).all()), "updates_max": int(iters.max()),
-            "sequential_ms": ms_seq, "speedup_of_newton": ms_seq / ms}
+    tol32 = 16 * 1.1920929e-7 * max(1.0, float(traj.abs().max()))
+    x32, p32 = x0.float(), prm.float()
+
+    def run32():
+        res["o32"] = P.solve(P.KURAMOTO, x32, p32, w.dt, T, tol=tol32, window=window)
+
+    ms32 = _time(run32, reps, stream)
+    tr32, it32, rs32, st32 = res["o32"]
+    out = {"instances": w.B, "T": T, "window": window, "ms": ms, "value": w.B * T / (ms / 1e3),
+           "all_ok": bool((status == 0).all()), "updates_max": int(iters.max()),
+           "sequential_ms": ms_seq, "speedup_of_newton": ms_seq / ms,
+           "fp32": {"ms": ms32, "value": w.B * T / (ms32 / 1e3), "tol": tol32,
+                    "all_ok": bool((st32 == 0).all()), "updates_max": int(it32.max())}}
+    samples = {"workload": w, "fp32": {i: tr32[i].double().cpu().numpy() for i in (0, 1)}}
+    return out, samples
+
+
+def cpu_leg(args, w, T, window, head_traj, head_fp32, checks):
+    """Everything that runs the CPU oracle: the headline's cpu_baseline (the
+    oracle's windowed Newton on the same workload, one thread), the oracle on
+    all host cores for the batched workloads (bounded samples), O1 on one
+    core, and the checks of GPU outputs against the oracle (FP64 defect of
+    the headline trajectory, FP32 error curves, the full-horizon dense scans
+    on their closed-form inputs)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    import workloads as W
+    host = host_cpu()
+    cores = host["usable_cores"]
+    out = {}
+    # the headline: the oracle as it stands, one thread, on a prefix of the workload
+    Ts = min(args.cpu_sample, T)
+    print(f"[bench] cpu oracle on the first {Ts} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    r = oracle.newton(w.system, w.params[0], w.dt, Ts, w.x0[0], tol=w.tol, window=window,
+                      max_iter=4 * Ts)
+    dt_cpu = time.perf_counter() - t0
+    cpu = {"value": Ts / dt_cpu, "unit": "converged steps*instances/s", "cores": 1,
+           "kind": "oracle", "host": host,
+           "sample": f"oracle windowed Newton (W={window}, tol 1e-10) on the first {Ts} "
+                     f"of the {T} steps, one instance, one thread: {dt_cpu:.1f} s, "
+                     f"{r['iters']} updates, status {r['status']}"}
+    # O1 (plain sequential RK4 on the CPU), one core, the whole headline horizon
+    t0 = time.perf_counter()
+    ref64 = oracle.integrate(w.system, w.params[0], w.dt, T, w.x0[0])
+    t_o1 = time.perf_counter() - t0
+    out["o1_sequential_one_core"] = {"value": T / t_o1, "unit": "steps/s", "cores": 1,
+                                     "seconds": t_o1}
+    # checks of the headline trajectories
+    h = oracle.residual(w.system, w.params[0], w.dt, w.x0[0], head_traj)
+    out["headline_fp64_defect"] = float(np.abs(h).max())
+    if head_fp32 is not None:
+        x0r = w.x0[0].astype(np.float32).astype(np.float64)
+        pr = w.params[0].astype(np.float32).astype(np.float64)
+        ref = oracle.integrate(w.system, pr, w.dt, T, x0r)
+        out["headline_fp32_err_vs_fp64_o1"] = err_curve(head_fp32, ref)
+    if not args.no_cpu_batches:
+        pool = ThreadPoolExecutor(max_workers=cores)
+        # C3: the whole van der Pol batch, windowed Newton (W = 64), all cores
+        wv = W.vdp_batch()
+        t0 = time.perf_counter()
+        rs = list(pool.map(lambda b: oracle.newton(wv.system, wv.params[b], wv.dt, int(wv.T[b]),
+                                                   wv.x0[b], tol=1e-10, window=64,
+                                                   max_iter=4 * int(wv.T[b]))["status"],
+                           range(wv.B)))
+        tv = time.perf_counter() - t0
+        out["vdp_batch_all_cores"] = {"value": float(wv.T.sum()) / tv,
+                                      "unit": "converged steps*instances/s", "cores": cores,
+                                      "seconds": tv, "all_ok": all(x == 0 for x in rs),
+                                      "sample": "the whole batch: 4096 instances, windowed Newton W=64"}
+        # C4: the sequential discrete adjoint (O3) on 64 of the 256 instances
+        wa = W.adjoint_l96()
+        obs = wa.extra["obs"] - 1
+        nb = 64
+
+        def adj(b):
+            tr = oracle.integrate(wa.system, wa.params[b], wa.dt, int(wa.T[b]), wa.x0[b])
+            g = np.zeros_like(tr)
+            g[obs] = 2 * (tr[obs] - wa.extra["y"][b])
+            return oracle.adjoint(wa.system, wa.params[b], wa.dt, wa.x0[b], tr, g)
+
+        t0 = time.perf_counter()
+        list(pool.map(adj, range(nb)))
+        ta = time.perf_counter() - t0
+        out["adjoint_all_cores"] = {"value": nb / ta, "unit": "grads/s", "cores": cores,
+                                    "seconds": ta,
+                                    "sample": f"{nb} of 256 instances: forward O1 + O3 each"}
+        # C5: the oracle's windowed Newton (W = 256) on the first 512 steps of all 8 instances
+        wk = W.kuramoto()
+        t0 = time.perf_counter()
+        list(pool.map(lambda b: oracle.newton(wk.system, wk.params[b], wk.dt, 512, wk.x0[b],
+                                              tol=1e-10, window=256, max_iter=4096),
+                      range(wk.B)))
+        tk = time.perf_counter() - t0
+        out["kuramoto_all_cores"] = {"value": wk.B * 512 / tk,
+                                     "unit": "converged steps*instances/s", "cores": cores,
+                                     "seconds": tk,
+                                     "sample": "first 512 of 4096 steps of all 8 instances"}
+        pool.shutdown()
+    # full-horizon dense scans against the oracle's recursion on the same inputs
+    for key, smp in checks.items():
+        if key.startswith("dense_fullT_"):
+            out[key + "_check"] = _check_fullT(oracle, smp)
+        elif key == "kuramoto":
+            wk = smp["workload"]
+            cur = {}
+            for i, got in smp["fp32"].items():
+                x0r = wk.x0[i].astype(np.float32).astype(np.float64)
+                pr = wk.params[i].astype(np.float32).astype(np.float64)
+                cur[f"instance_{i}"] = err_curve(got, oracle.integrate(wk.system, pr, wk.dt,
+                                                                       len(got), x0r))
+            out["kuramoto_fp32_err_vs_fp64_o1"] = cur
+    return cpu, out
+
+
+def _check_fullT(oracle, smp):
+    """Per-step relative error of sampled full-horizon scan outputs against
+    the oracle's recursion z_{n+1} = A z_n + b from z_0 = 0, with the
+    oracle's A = dPhi/dx(x0), b = Phi(x0) - x0 (rounded to FP32 for the FP32
+    scan), evaluated in chunks of 256 elements."""
+    w, ncheck = smp["workload"], smp["ncheck"]
+    out = {}
+    for prec, zs in (("fp64", smp["fp64"]), ("fp32", smp["fp32"])):
+        for i, got in zs.items():
+            Aw = oracle.rk4_jac(w.system, w.params[i], w.dt, w.x0[i])
+            bw = oracle.rk4_step(w.system, w.params[i], w.dt, w.x0[i]) - w.x0[i]
+            if prec == "fp32":
+                Aw = Aw.astype(np.float32).astype(np.float64)
+                bw = bw.astype(np.float32).astype(np.float64)
+            ref = np.empty((ncheck, w.d))
+            z = None
+            for c0 in range(0, ncheck, 256):
+                n = min(256, ncheck - c0)
+                ref[c0:c0 + n] = oracle.affine_seq(np.broadcast_to(Aw, (n,) + Aw.shape).copy(),
+                                                   np.broadcast_to(bw, (n,) + bw.shape).copy(), z)
+                z = ref[c0 + n - 1].copy()
+            c = err_curve(got, ref, bar=1e-4 if prec == "fp32" else 1e-10)
+            c["max_rel_err"] = float(np.max(np.abs(got - ref)) / max(1.0, float(np.abs(ref).max())))
+            out[f"{prec}_instance_{i}"] = c
+    return out
 
 
 def main():
@@ -372,7 +578,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=65536, help="oracle prefix length (steps)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip every oracle run (CPU leg)")
+    ap.add_argument("--no-cpu-batches", action="store_true",
+                    help="CPU leg: skip the all-core oracle timings of the batched workloads")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and comparator legs")
     ap.add_argument("--legs", default="scan,dense,vdp,adjoint,kuramoto,parareal,implicit",
                     help="extra workloads to measure (comma list, or 'none')")
@@ -451,17 +659,11 @@ def main():
     print(f"[bench] fp64 solve: {ms_per_step:.3f} ms/solve, status={st}, updates={n_iter}, "
           f"resid={r_final:.3e}", file=sys.stderr, flush=True)
     value = B * T / (ms_per_step / 1e3)
-
-    # FP64 defect of the returned trajectory, by the oracle's RK4 (checking only)
-    defect = None
-    try:
-        import oracle
-        h = oracle.residual(w.system, w.params[0], w.dt, w.x0[0], traj[0].cpu().numpy())
-        defect = float(np.abs(h).max())
-    except Exception as e:  # pragma: no cover
-        print(f"[bench] defect check skipped: {e}", file=sys.stderr)
+    head_traj = traj[0].cpu().numpy()
+    head_fp32 = None
 
     extra = {}
+    checks = {}
     if not args.no_extra:
         # sequential RK4 on the GPU (the comparator), same inputs
         T_off = torch.tensor([0, T], dtype=torch.int64, device=dev)
@@ -493,14 +695,7 @@ def main():
         ms32 = e0.elapsed_time(e1) / max(1, args.steps // 2)
         fp32 = {"value": B * T / (ms32 / 1e3), "ms_per_solve": ms32, "status": int(st32[0]),
                 "updates": int(it32[0]), "tol": 2e-5}
-        try:
-            import oracle
-            got = tr32[0].double().cpu().numpy()
-            ref = oracle.integrate(w.system, w.params[0].astype(np.float32).astype(np.float64),
-                                   w.dt, 200, w.x0[0].astype(np.float32).astype(np.float64))
-            fp32["max_rel_err_vs_fp64_first200"] = float(np.abs(got[:200] - ref).max() / np.abs(ref).max())
-        except Exception:
-            pass
+        head_fp32 = tr32[0].double().cpu().numpy()
         extra["fp32"] = fp32
 
     legs = [] if args.legs in ("", "none") else args.legs.split(",")
@@ -509,14 +704,15 @@ def main():
         if leg == "scan":
             extra["scan_small_d"] = leg_scan_small(P, torch, dev, stream)
         elif leg == "dense":
-            extra["dense_fullT_lorenz96"] = leg_dense_fullT(P, torch, dev, stream, "lorenz96")
-            extra["dense_fullT_kuramoto"] = leg_dense_fullT(P, torch, dev, stream, "kuramoto")
+            for which in ("lorenz96", "kuramoto"):
+                extra["dense_fullT_" + which], checks["dense_fullT_" + which] = \
+                    leg_dense_fullT(P, torch, dev, stream, which)
         elif leg == "vdp":
             extra["vdp_batch"] = leg_vdp_batch(P, torch, dev, stream)
         elif leg == "adjoint":
             extra["adjoint_lorenz96"] = leg_adjoint(P, torch, dev, stream)
         elif leg == "kuramoto":
-            extra["kuramoto"] = leg_kuramoto(P, torch, dev, stream)
+            extra["kuramoto"], checks["kuramoto"] = leg_kuramoto(P, torch, dev, stream)
         elif leg == "paper":
             extra["paper_runtime"] = leg_paper_runtime(P, torch, dev, stream)
         elif leg == "implicit":
@@ -536,20 +732,9 @@ def main():
                 "traffic_source": tinfo,
                 "algorithmic_flops_per_launch": alg_flops, "launch_ms": launch_ms}
 
-    cpu = None
+    cpu, cpu_checks = None, None
     if not args.no_cpu:
-        import oracle
-        Ts = min(args.cpu_sample, T)
-        print(f"[bench] cpu oracle on the first {Ts} steps", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        r = oracle.newton(w.system, w.params[0], w.dt, Ts, w.x0[0], tol=w.tol, window=args.window,
-                          max_iter=4 * Ts)
-        dt_cpu = time.perf_counter() - t0
-        cpu = {"value": Ts / dt_cpu, "unit": "converged steps*instances/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"oracle windowed Newton (W={args.window}, tol 1e-10) on the first {Ts} "
-                         f"of the {T} steps, one instance, one thread: {dt_cpu:.1f} s, "
-                         f"{r['iters']} updates, status {r['status']}"}
+        cpu, cpu_checks = cpu_leg(args, w, T, args.window, head_traj, head_fp32, checks)
 
     out = {
         "metric": "converged steps*instances/sec (scan vs sequential, 1e-10 err); adjoint grads/sec",
@@ -563,9 +748,11 @@ def main():
                    "window_tuning": None if tuned is None else
                    {str(t["window"]): round(t["ms"], 2) for t in tuned["trials"]},
                    "parallelism": "single GPU"},
-        "solve": {"status": st, "updates": n_iter, "final_resid": r_final, "fp64_defect": defect},
+        "solve": {"status": st, "updates": n_iter, "final_resid": r_final,
+                  "fp64_defect": None if cpu_checks is None else cpu_checks["headline_fp64_defect"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_oracle": cpu_checks,
         **extra,
     }
     print(json.dumps(out), flush=True)

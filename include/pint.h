@@ -137,6 +137,18 @@ typedef struct {
 #define PINT_WAIT_LIMIT_DEFAULT 268435456ull
 void pint_set_wait_limit(uint64_t polls);
 
+/* Test hook of the decoupled-lookback scans (pint_affine_scan, its
+ * no-alloc variant, pint_affine_scan_band and the adjoint's scans): with
+ * sleeps > 0, tile t sleeps `sleeps` short intervals before it publishes its
+ * aggregate when t % 3 == 1, and before it publishes its inclusive prefix
+ * when t % 3 == 2, so that successors meet unpublished and aggregate-only
+ * predecessors and take the longer lookback paths.  Results stay correct
+ * (up to the rounding of a different composition order); only the timing
+ * changes.  Process-wide; applies to launches enqueued after the call;
+ * 0 (the default) turns it off.  The lookback's own bounded wait still
+ * applies: keep sleeps small (a few hundred at most). */
+void pint_set_scan_delay(uint32_t sleeps);
+
 /* Number of parameters of `system` at dimension d, or -1 if not allowed. */
 int pint_n_params(int32_t system, int32_t d);
 
@@ -305,7 +317,10 @@ pint_status pint_elements(const pint_system* sys, int64_t B, const void* x0,
  * PINT_OK at once when B or N is 0; PINT_ERR_INVALID_ARG for d < 1,
  * negative sizes or tile, another dtype, or a NULL A, b or z;
  * PINT_ERR_UNSUPPORTED for a d outside the list; PINT_ERR_WORKSPACE when
- * ws is NULL or smaller than the query. */
+ * ws is NULL or smaller than the query.  Each tile's wait for its
+ * predecessors is bounded (2^24 polls); a wait that gives up sets the 32-bit
+ * word at byte offset 4 of ws to nonzero (it is zeroed at the start of every
+ * call) and the result is then unreliable: a caller that syncs can read it. */
 size_t pint_scan_workspace_bytes(int32_t d, int64_t B, int64_t N, int32_t tile,
                                  int32_t dtype);
 pint_status pint_affine_scan(int32_t d, int64_t B, int64_t N, int32_t dtype,

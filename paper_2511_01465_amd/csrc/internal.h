@@ -77,6 +77,10 @@ int parareal(const SolveArgs& a, int64_t M, int64_t S, double* hist);
 // (process-wide; set through pint_set_wait_limit).
 uint64_t wait_limit();
 
+// Test hook of the decoupled-lookback scans (process-wide; set through
+// pint_set_scan_delay): sleeps injected before some tiles publish.
+uint32_t scan_delay();
+
 // Zero `n` 32-bit words with a kernel (no memset nodes in captured graphs).
 int fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 

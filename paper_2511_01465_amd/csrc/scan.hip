@@ -46,6 +46,7 @@ struct ScanArgs {
   uint32_t* flags;         // [B * tiles_per_seq]
   void* agg;               // [B * tiles_per_seq][D*D + D]
   void* incl;              // [B * tiles_per_seq][D]
+  uint32_t delay;          // test hook: sleeps before some publishes (0 = off)
 };
 
 constexpr uint32_t FLAG_AGG = 1, FLAG_INCL = 2;
@@ -64,9 +65,17 @@ __device__ __forceinline__ T ld_payload(const T* p) {
 // Called by the thread that stored the payload (or after a workgroup barrier,
 // which itself waits for every wave's stores): the payload stores complete
 // before the flag store is issued.
-__device__ __forceinline__ void publish_flag(uint32_t* f, uint32_t v) {
+// With the test hook `delay` set, tile ts sleeps `delay` times before it
+// publishes its aggregate when ts % 3 == 1, and before it publishes its
+// inclusive prefix when ts % 3 == 2: successors then find predecessors not
+// yet published, or published as aggregate only, and must wait for them or
+// look further back.
+__device__ __forceinline__ void publish_flag(uint32_t* flags, int64_t ts, uint32_t v,
+                                             uint32_t delay) {
+  if (delay != 0 && ts % 3 == (int64_t)v)
+    for (uint32_t i = 0; i < delay; i++) __builtin_amdgcn_s_sleep(16);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(flags + ts, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wave-parallel lookback search (all 64 lanes of one wave call it): lanes
@@ -341,7 +350,7 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
         for (int i = 0; i < D * D; i++) st_payload(aggp + ts * E + i, s_tagg.A[i]);
 #pragma unroll
         for (int i = 0; i < D; i++) st_payload(aggp + ts * E + D * D + i, s_tagg.b[i]);
-        publish_flag(flags + ts, FLAG_AGG);
+        publish_flag(flags, ts, FLAG_AGG, a.delay);
       }
       // acc = composition of the aggregates passed so far (newest applied last)
       Aff<T, D> acc;
@@ -423,7 +432,7 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
         for (int q = 0; q < D; q++) t += s_tagg.A[i * D + q] * z[q];
         st_payload(inclp + ts * D + i, t);
       }
-      publish_flag(flags + ts, FLAG_INCL);
+      publish_flag(flags, ts, FLAG_INCL, a.delay);
     }
     if (nch > 1) fetch(nch - 2);
   }
@@ -680,7 +689,7 @@ __global__ __launch_bounds__(64) void k_scan_wide(ScanArgs a) {
   } else {
     for (int i = lane; i < E; i += NT) st_payload(aggp + ts * E + i, sT[i]);
     if (lane == 0) {
-      publish_flag(flags + ts, FLAG_AGG);
+      publish_flag(flags, ts, FLAG_AGG, a.delay);
       aff_identity_lds<T, D>(sAcc);
     }
     __syncthreads();
@@ -744,7 +753,7 @@ __global__ __launch_bounds__(64) void k_scan_wide(ScanArgs a) {
     for (int q = 0; q < D; q++) t += sT[lane * D + q] * sZ[q];
     st_payload(inclp + ts * D + lane, t);
   }
-  if (lane == 0) publish_flag(flags + ts, FLAG_INCL);
+  if (lane == 0) publish_flag(flags, ts, FLAG_INCL, a.delay);
 
   // outputs of this lane's run, from z at its start (the previous lane's
   // inclusive prefix applied to z_in)
@@ -869,7 +878,7 @@ __device__ void tile_prefix(const ScanArgs& a, int64_t seq, int64_t ts, const T*
     for (int idx = tid; idx < D * D; idx += NT) st_payload(aggp + ts * E + idx, sP[(idx / D) * PS + idx % D]);
     for (int i = tid; i < D; i += NT) st_payload(aggp + ts * E + D * D + i, sq[i]);
     __syncthreads();
-    if (tid == 0) publish_flag(flags + ts, FLAG_AGG);
+    if (tid == 0) publish_flag(flags, ts, FLAG_AGG, a.delay);
     if (wv == 0) {
       // nearest predecessor whose inclusive prefix is known
       int64_t end = ts - 1;
@@ -903,7 +912,7 @@ __device__ void tile_prefix(const ScanArgs& a, int64_t seq, int64_t ts, const T*
     for (int off = 1; off < QC; off <<= 1) part += __shfl_xor(part, off, PINT_WAVE);
     if (i < D && q == 0) st_payload(inclp + ts * D + i, part + sq[i]);
     __syncthreads();
-    if (tid == 0) publish_flag(flags + ts, FLAG_INCL);
+    if (tid == 0) publish_flag(flags, ts, FLAG_INCL, a.delay);
   }
 }
 
@@ -1557,6 +1566,7 @@ int affine_scan(int d, int64_t B, int64_t N, int dtype, const void* A, const voi
   sa.flags = reinterpret_cast<uint32_t*>(w + 256);
   sa.agg = w + 256 + align_up((size_t)nt * 4);
   sa.incl = w + 256 + align_up((size_t)nt * 4) + align_up((size_t)nt * (d * d + d) * sz);
+  sa.delay = scan_delay();
   // reset the tile counter, error word and flags (a kernel, not a memset)
   if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w), 64 + (size_t)nt, 0u, s)) return rc;
 #define PINT_CASE_SMALL(DD) \
@@ -1649,6 +1659,7 @@ int affine_scan_band(int d, int bw, int boff, int64_t B, int64_t N, int dtype, c
   sa.flags = reinterpret_cast<uint32_t*>(w + 256);
   sa.agg = w + 256 + align_up((size_t)nt * 4);
   sa.incl = w + 256 + align_up((size_t)nt * 4) + align_up((size_t)nt * (d * d + d) * sz);
+  sa.delay = scan_delay();
   if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w), 64 + (size_t)nt, 0u, s)) return rc;
   if (boff == 4) return dtype == 0 ? launch_band<double, 4>(sa, nt, s) : launch_band<float, 4>(sa, nt, s);
   return dtype == 0 ? launch_band<double, 8>(sa, nt, s) : launch_band<float, 8>(sa, nt, s);
