@@ -149,6 +149,15 @@ void pint_set_wait_limit(uint64_t polls);
  * applies: keep sleeps small (a few hundred at most). */
 void pint_set_scan_delay(uint32_t sleeps);
 
+/* Which cooperative solver runs windowed Lorenz-96 solves (pint_solve of
+ * PINT_SYS_LORENZ96, d = 40, window >= 1, batches of up to 1/4 as many
+ * instances as compute units): on != 0 (the default) the pipelined solver,
+ * in which consecutive Newton updates overlap in time on separate
+ * workgroups; 0 the solver that applies one update at a time.  Both compute
+ * the same iteration (same windows, same accepted updates).  Process-wide;
+ * applies to launches enqueued after the call. */
+void pint_set_dense_pipeline(int on);
+
 /* Number of parameters of `system` at dimension d, or -1 if not allowed. */
 int pint_n_params(int32_t system, int32_t d);
 

@@ -62,7 +62,7 @@ EXPORTS = ["pint_n_params", "pint_status_string", "pint_supported", "pint_worksp
            "pint_adjoint_workspace_bytes", "pint_adjoint", "pint_graph_capture_varlen",
            "pint_graph_launch", "pint_graph_destroy", "pint_set_wait_limit",
            "pint_parareal_workspace_bytes", "pint_parareal", "pint_affine_scan_noalloc",
-           "pint_set_scan_delay"]
+           "pint_set_scan_delay", "pint_set_dense_pipeline"]
 
 # include/pint.h: PINT_WAIT_LIMIT_DEFAULT
 WAIT_LIMIT_DEFAULT = 268435456
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
         "pint_graph_destroy": (C.c_int, [vp]),
         "pint_set_wait_limit": (None, [C.c_uint64]),
         "pint_set_scan_delay": (None, [C.c_uint32]),
+        "pint_set_dense_pipeline": (None, [C.c_int]),
         "pint_parareal_workspace_bytes": (sz, [SP, i64, i64, i32]),
         "pint_affine_scan_noalloc": (C.c_int, [i32, i64, i64, i32, vp, vp, vp, vp, i32, vp, vp]),
         "pint_parareal": (C.c_int, [SP, i64, vp, dbl, i64, i64, OP, vp, vp, vp, vp, vp, vp, sz, vp]),
@@ -287,6 +288,10 @@ def pint_set_wait_limit(polls: int) -> None:
 
 def pint_set_scan_delay(sleeps: int) -> None:
     load().pint_set_scan_delay(int(sleeps))
+
+
+def pint_set_dense_pipeline(on: bool) -> None:
+    load().pint_set_dense_pipeline(1 if on else 0)
 
 
 def pint_parareal_workspace_bytes(sysd, B, M, dtype) -> int:

@@ -93,11 +93,13 @@ SolveArgs make_args(const pint_system* sys, int64_t B, const void* x0, double dt
 
 uint64_t g_wait_limit = PINT_WAIT_LIMIT_DEFAULT;
 uint32_t g_scan_delay = 0;
+int g_dense_pipeline = 1;
 
 }  // namespace
 
 uint64_t pint::wait_limit() { return __atomic_load_n(&g_wait_limit, __ATOMIC_RELAXED); }
 uint32_t pint::scan_delay() { return __atomic_load_n(&g_scan_delay, __ATOMIC_RELAXED); }
+bool pint::dense_pipeline() { return __atomic_load_n(&g_dense_pipeline, __ATOMIC_RELAXED) != 0; }
 
 extern "C" {
 
@@ -106,6 +108,8 @@ int pint_n_params(int32_t system, int32_t d) { return n_params_of(system, d); }
 void pint_set_wait_limit(uint64_t polls) { __atomic_store_n(&g_wait_limit, polls, __ATOMIC_RELAXED); }
 
 void pint_set_scan_delay(uint32_t sleeps) { __atomic_store_n(&g_scan_delay, sleeps, __ATOMIC_RELAXED); }
+
+void pint_set_dense_pipeline(int on) { __atomic_store_n(&g_dense_pipeline, on ? 1 : 0, __ATOMIC_RELAXED); }
 
 const char* pint_status_string(int32_t s) {
   switch (s) {

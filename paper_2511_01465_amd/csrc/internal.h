@@ -48,6 +48,13 @@ int small_residual(const SolveArgs& a, void* h, double* hmax);
 int small_elements(const SolveArgs& a, void* A, void* b);
 
 size_t dense_ws_bytes(const SolveArgs& a);
+// The pipelined windowed solver for Lorenz-96 (newton_pipe.hip): workspace
+// bytes (0 when it does not apply) and the launch (*used: whether it ran).
+size_t pipe_ws_bytes(const SolveArgs& a);
+int pipe_solve(const SolveArgs& a, bool* used);
+// Process-wide switch between the pipelined solver and the one-update-at-a-
+// time cooperative solver (pint_set_dense_pipeline); on by default.
+bool dense_pipeline();
 int dense_solve(const SolveArgs& a);
 int dense_seq(const SolveArgs& a);
 int dense_residual(const SolveArgs& a, void* h, double* hmax);

@@ -1138,11 +1138,17 @@ size_t dense_ws_bytes(const SolveArgs& a) {
     total = dense_ws_layout<T, S>(a).total;
     return ST_OK;
   });
-  return total;
+  const size_t pipe = pipe_ws_bytes(a);
+  return total > pipe ? total : pipe;
 }
 
 int dense_solve(const SolveArgs& a) {
   if (!a.ws || a.ws_bytes < dense_ws_bytes(a)) return ST_WORKSPACE;
+  if (dense_pipeline()) {  // Lorenz-96, windowed: the pipelined solver when it fits
+    bool used = false;
+    if (int rc = pipe_solve(a, &used)) return rc;
+    if (used) return ST_OK;
+  }
   return dispatch_dense(a.dtype, a.system, a.d, [&](auto t, auto s) -> int {
     using T = decltype(t);
     using S = decltype(s);

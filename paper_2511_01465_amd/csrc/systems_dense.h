@@ -143,18 +143,32 @@ struct DSysL96 {
     const T h2 = T(0.5) * dt, c6 = dt / T(6);
     T u[BW], acc[BW];
 #pragma unroll
-    for (int r = 0; r < BW; r++) u[r] = (r == LO) ? T(1) : T(0);
+    for (int r = 0; r < BW; r++) {
+      u[r] = (r == LO) ? T(1) : T(0);
+      acc[r] = T(0);
+    }
 #pragma unroll
     for (int s = 0; s < 4; s++) {
+      // before stage s the tangent is nonzero only in rows LO - s .. LO + 2s
+      // (each stage's stencil reaches one row down and two up), so the
+      // stage's product is nonzero only in rows LO - 1 - s .. LO + 2 + 2s;
+      // the other rows keep their exact zeros
+      const int r0 = LO - 1 - s > 0 ? LO - 1 - s : 0;
+      const int r1 = LO + 2 + 2 * s < BW - 1 ? LO + 2 + 2 * s : BW - 1;
       const T* x = st->x[s];
       T y[YW];
 #pragma unroll
-      for (int w = 0; w < YW; w++) y[w] = x[yi[w]];
+      for (int w = 0; w < YW; w++)
+        if (w >= r0 && w <= r1 + 3) y[w] = x[yi[w]];
       const T w_s = (s == 0 || s == 3) ? T(1) : T(2);
       const T c = (s == 2) ? dt : h2;
       T un[BW];
 #pragma unroll
       for (int r = 0; r < BW; r++) {
+        if (r < r0 || r > r1) {
+          un[r] = u[r];
+          continue;
+        }
         // row i = j - LO + r: y_{i-1} = y[r+1], y_{i+1} = y[r+3], y_{i-2} = y[r]
         const T up1 = r + 1 < BW ? u[r + 1] : T(0);
         const T um1 = r >= 1 ? u[r - 1] : T(0);
