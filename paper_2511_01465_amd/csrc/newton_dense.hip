@@ -452,7 +452,7 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
           T bv[BW];
 #pragma unroll
           for (int k = 0; k < BW; k++) bv[k] = band[k * D + row];
-          T a0 = L[CH * NB + m * D + row], a1 = T(0);
+          T z = L[CH * NB + m * D + row];
           if (c0 + m > 0) {
             T nb[BW];
             nb[BOFF] = zr;
@@ -468,15 +468,8 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
               t = dpp_row<DPP_WAVE_SHL1, 0xf>(T(0), t);
               nb[BOFF + q] = t;
             }
-#pragma unroll
-            for (int k = 0; k < BW; k++) {
-              if (k & 1)
-                a1 += bv[k] * nb[k];
-              else
-                a0 += bv[k] * nb[k];
-            }
+            z = band_row13<T>(z, bv, nb);
           }
-          T z = a0 + a1;
           // copies take their owner's new value
           if constexpr (sizeof(T) == 8) {
             const int lo = __builtin_amdgcn_ds_bpermute(src * 4, __double2loint((double)z));
@@ -510,7 +503,7 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
         const T* L = lbuf + (size_t)(c & 1) * CH * PER;
         for (int m = 0; m < n; m++) {
           const T* band = L + m * NB;
-          T a0 = L[CH * NB + m * D + i], a1 = T(0);
+          T z = L[CH * NB + m * D + i];
           if (c0 + m > 0) {
             // issue all LDS reads of the step, then the multiply-adds
             T bv[BW], zv[BW];
@@ -520,15 +513,8 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
               zv[k] = zx[i + k];
             }
             __builtin_amdgcn_sched_barrier(0);
-  #pragma unroll
-            for (int k = 0; k < BW; k++) {
-              if (k & 1)
-                a1 += bv[k] * zv[k];
-              else
-                a0 += bv[k] * zv[k];
-            }
+            z = band_row13<T>(z, bv, zv);
           }
-          const T z = a0 + a1;
           if (lane < D) {
             zx[i + BOFF] = z;
             if (i >= D - BOFF) zx[i + BOFF - D] = z;

@@ -14,11 +14,11 @@
 //
 // G workgroups ("agents", one per compute unit, cooperative launch) take the
 // updates round robin: agent g runs updates g+1, g+1+G, ...  Inside an agent
-// (12 waves), for its update u:
+// (8 waves), for its update u:
 //   wave 1 (loader)   streams the states of iterate u-1 from the trajectory
 //                     into an LDS ring as they become final (as the agent of
 //                     update u-1 publishes them), x_m for m = p_{u-1}-1, ...;
-//   7 waves           build the element of each staged state: Phi(x_m) and
+//   4 waves           build the element of each staged state: Phi(x_m) and
 //                     the 13-diagonal band of dPhi/dx(x_m), into the ring;
 //   wave 0 (fold)     evaluates the residuals from the ring to find p_u,
 //                     then folds dx_n = J_{n-1} dx_{n-1} - h_n over the
@@ -56,16 +56,17 @@ struct alignas(64) PipeCtl {
 static_assert(sizeof(PipeRec) == 64 && sizeof(PipeCtl) == 64, "control block sizes");
 
 constexpr unsigned long long DONE_BIT = 1ull << 63;
-// 12 waves.  Waves are spread over the compute unit's four SIMDs in turn
-// (wave w on SIMD w % 4), so waves 4 and 8 stay idle: the fold (wave 0) then
-// has its SIMD to itself and is never held up behind the element waves'
-// multiply-adds.  Wave 1 loads, wave 2 writes, the other seven build
-// elements.
-constexpr int PIPE_NT = 768;
-constexpr int PIPE_NE = 7;
+// 8 waves.  Waves are spread over the compute unit's four SIMDs in turn
+// (wave w on SIMD w % 4), so wave 4 stays idle: the fold (wave 0) then has
+// its SIMD to itself and is never held up behind the element waves'
+// multiply-adds.  Wave 1 loads, wave 2 writes, waves 3, 5, 6 and 7 build
+// elements (one of them alone on its SIMD, the others beside the light
+// loader and writer).  Two waves per SIMD leave each up to 256 registers.
+constexpr int PIPE_NT = 512;
+constexpr int PIPE_NE = 4;
 __device__ __forceinline__ int pipe_elem_index(int wv) {
-  // waves 3, 5, 6, 7, 9, 10, 11 -> 0..6; -1 for the others
-  return wv == 3 ? 0 : (wv >= 5 && wv <= 7) ? wv - 4 : (wv >= 9 && wv <= 11) ? wv - 5 : -1;
+  // waves 3, 5, 6, 7 -> 0..3; -1 for the others
+  return wv == 3 ? 0 : (wv >= 5 && wv <= 7) ? wv - 4 : -1;
 }
 constexpr int PIPE_R = 24;      // ring slots (steps)
 
@@ -180,6 +181,7 @@ template <typename T, class S>
 __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
   constexpr int D = S::D, BW = S::BW, BOFF = S::BOFF, R = PIPE_R;
   static_assert(D <= PINT_WAVE && S::R == 1, "one lane per component");
+  static_assert(BW == 13, "the row sum is written for 13 diagonals");
   extern __shared__ __align__(16) unsigned char dyn[];
   PipeSmem<T, S>& sm = *reinterpret_cast<PipeSmem<T, S>*>(dyn);
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
@@ -442,56 +444,65 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
           wg_release();
           lds_st(&sm.p_u, p);
         }
-        // dx_p = -h_p, then dx_n = J(x_{n-1}) dx_{n-1} - h_n
+        // dx_p = -h_p, then dx_n = J(x_{n-1}) dx_{n-1} - h_n.  Software
+        // pipelined: the operands of step n+1 (its band row, Phi(x_n),
+        // x_{n+1} and the neighbours of dx_n) are loaded during step n, as
+        // soon as dx_n is written and step n+1's flags (read at the start of
+        // step n) show them in the ring.
         T dx = -h;
         int last = p - 1;
-        bool next_ready = false;  // the flags of step n, read during step n-1
+        T bv[BW], zv[BW], phc = T(0), xc = sm.sx[sc][i];
+        auto load_ops = [&]() {  // operands of step n from slots sp (element n-1) and sc (state n)
+          // the neighbours of dx first: they are the step's critical path
+#pragma unroll
+          for (int k = 0; k < BW; k++) zv[k] = sm.zx[i + k];
+          const T* band = sm.sband[sp];
+#pragma unroll
+          for (int k = 0; k < BW; k++) bv[k] = band[k * D + i];
+          phc = sm.sphi[sp][i];
+          xc = sm.sx[sc][i];
+        };
         for (;;) {
-          // read step n+1's flags now; they are checked after this step
+          // step n+1's flags, read now, checked once dx_n is written
           const int sn = sc + 1 == R ? 0 : sc + 1;
           const int fr1 = lds_ld(&sm.ready[sc]), fs1 = lds_ld(&sm.staged[sn]), fw1 = lds_ld(&sm.written);
-          if (n > p) {
-            if (!next_ready && !await(p)) {
-              stop = true;
-              break;
-            }
-            const T* band = sm.sband[sp];
-            T bv[BW], zv[BW];
-#pragma unroll
-            for (int k = 0; k < BW; k++) {
-              bv[k] = band[k * D + i];
-              zv[k] = sm.zx[i + k];
-            }
-            T a0 = sm.sphi[sp][i] - sm.sx[sc][i], a1 = T(0);
-#pragma unroll
-            for (int k = 0; k < BW; k++) {
-              if (k & 1)
-                a1 += bv[k] * zv[k];
-              else
-                a0 += bv[k] * zv[k];
-            }
-            dx = a0 + a1;
-          }
-          const T xn = sm.sx[sc][i] + dx;
-          const bool bad = lane < D && (!finite_(xn) || fabs((double)xn) > a.guard);
-          if (__ballot(bad)) break;
-          if (lane < D) {
-            sm.xo[sc][i] = xn;
-            // the previous dx for the next step, with the wrap-around copies
+          if (n > p) dx = band_row13<T>(phc - xc, bv, zv);
+          const T xn = xc + dx;
+          if (lane < D) {  // dx_n for the next step, with the wrap-around copies
             sm.zx[i + BOFF] = dx;
             if (i >= D - BOFF) sm.zx[i + BOFF - D] = dx;
             if (i + BOFF + D < D + BW - 1) sm.zx[i + BOFF + D] = dx;
           }
+          const bool more = n < e;
+          const bool next_ready =
+              more && (fr1 == n) & (fs1 == n + 1) & (n + 1 - R < p || fw1 >= n + 1 - R);
+          const int sp0 = sp, sc0 = sc;
+          if (next_ready) {
+            wg_acquire();
+            sp = sc;  // (advance() below repeats this; the loads need the new slots now)
+            sc = sn;
+            load_ops();  // after the zx writes: one wave's LDS operations complete in order
+            sp = sp0;
+            sc = sc0;
+          }
+          const bool bad = lane < D && (!finite_(xn) || fabs((double)xn) > a.guard);
+          if (__ballot(bad)) break;
+          if (lane < D) sm.xo[sc][i] = xn;
           wg_release();
           if (lane == 0) {
             lds_st(&sm.out_ready, n);
             lds_st(&sm.f_pos, n);
           }
           last = n;
-          if (n == e) break;
-          next_ready = (fr1 == n) & (fs1 == n + 1) & (n + 1 - R < p || fw1 >= n + 1 - R);
-          if (next_ready) wg_acquire();
+          if (!more) break;
           advance();
+          if (!next_ready) {
+            if (!await(p)) {
+              stop = true;
+              break;
+            }
+            load_ops();
+          }
         }
         if (!stop && last == p - 1) {  // the first updated state is unusable
           if (lane == 0) pipe_finish(c, ST_NONFINITE, u - 1);

@@ -21,6 +21,27 @@ struct StageKur {
   T C[4], S[4];
 };
 
+// One row of the banded recursion, b + sum_k band[k] * z[k] over the 13
+// diagonals of the Lorenz-96 step Jacobian: the 13 products are independent,
+// then summed as a balanced tree (a short dependency chain behind the
+// operand loads).  Every solver that folds banded Lorenz-96 elements uses
+// this one expression, so their results agree bit for bit.
+// Products and sums are spelled out (fma, then rounded adds) so that no
+// compiler contraction can make two call sites round differently.
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+template <typename T>
+__device__ __forceinline__ T band_row13(T b, const T (&bv)[13], const T (&z)[13]) {
+  T q[6];
+#pragma unroll
+  for (int k = 0; k < 6; k++) q[k] = fma(bv[2 * k], z[2 * k], mul_rn(bv[2 * k + 1], z[2 * k + 1]));
+  const T s0 = add_rn(q[0], q[1]), s1 = add_rn(q[2], q[3]), s2 = add_rn(q[4], q[5]);
+  const T t = fma(bv[12], z[12], b);
+  return add_rn(add_rn(s0, s1), add_rn(s2, t));
+}
+
 // ------------------------------------------------------------ Lorenz-96 --
 
 // f_i = (x_{i+1} - x_{i-2}) x_{i-1} - x_i + F, indices mod D (D <= 64).
