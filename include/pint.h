@@ -149,13 +149,17 @@ void pint_set_wait_limit(uint64_t polls);
  * applies: keep sleeps small (a few hundred at most). */
 void pint_set_scan_delay(uint32_t sleeps);
 
-/* Which cooperative solver runs windowed Lorenz-96 solves (pint_solve of
- * PINT_SYS_LORENZ96, d = 40, window >= 1, batches of up to 1/4 as many
- * instances as compute units): on != 0 (the default) the pipelined solver,
- * in which consecutive Newton updates overlap in time on separate
- * workgroups; 0 the solver that applies one update at a time.  Both compute
- * the same iteration (same windows, same accepted updates).  Process-wide;
- * applies to launches enqueued after the call. */
+/* The pipelined Lorenz-96 kernels (d = 40), on != 0 by default:
+ *  - windowed solves (pint_solve of PINT_SYS_LORENZ96, window >= 1, batches
+ *    of up to 1/4 as many instances as compute units): the pipelined
+ *    solver, in which consecutive Newton updates overlap in time on separate
+ *    workgroups; 0 the solver that applies one update at a time.  Both
+ *    compute the same iteration (same windows, same accepted updates).
+ *  - pint_adjoint: the fused reverse pass, elements built inside the
+ *    recursion; 0 the two-kernel path (elements stored per segment, then
+ *    the banded scan).  Same recursion, summation order aside.
+ * Process-wide; applies to launches enqueued (and workspace queries made)
+ * after the call. */
 void pint_set_dense_pipeline(int on);
 
 /* Number of parameters of `system` at dimension d, or -1 if not allowed. */
@@ -398,6 +402,13 @@ pint_status pint_affine_scan_band(int32_t d, int32_t bw, int32_t boff, int64_t B
  *   seg       steps per recomputation segment: elements are recomputed from
  *             traj segment by segment (memory seg*d*d per instance); 0 = T
  *             (all elements at once).
+ * Lorenz-96 (d = 40) builds each element inside the reverse recursion and
+ * stores none (one workgroup per instance): seg is then ignored and the
+ * workspace query returns a small constant.  pint_set_dense_pipeline(0)
+ * selects the two-kernel path instead (elements of a segment written, then
+ * scanned); query the workspace after setting it.  In the fused pass a
+ * bounded wait between the workgroup's waves that gives up (not expected)
+ * leaves NaN in that instance's outputs.
  */
 size_t pint_adjoint_workspace_bytes(const pint_system* sys, int64_t B, int64_t T,
                                     int64_t seg, int32_t dtype);

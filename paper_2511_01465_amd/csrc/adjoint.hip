@@ -286,6 +286,205 @@ __global__ __launch_bounds__(256) void k_adj_theta_l96(AdjArgs a, const T* lam, 
   if (lane == 0) atomicAdd(dth + inst, part);
 }
 
+// ------------------------------------------- Lorenz-96, fused reverse pass --
+
+// The whole reverse recursion of one Lorenz-96 instance in one workgroup,
+// with the transposed elements built just before they are used and never
+// stored: lambda_T = g_T, lambda_n = g_n + J(x_n)^T lambda_{n+1} for
+// n = T-1 .. 1, dL/dx0 = J(x_0)^T lambda_1, and
+// dL/dF = sum_{n=0}^{T-1} S(x_n) . lambda_{n+1} (S = dPhi/dF).
+//
+// Eight waves.  Six builder waves (1, 2, 3, 5, 6, 7) take the elements
+// i = T - n round robin: each loads x_n and g_n, runs the RK4 stages, and
+// puts into an LDS ring of AP_R slots the band of row j of J(x_n)^T for
+// every j (column j of J over the 13 rows its tangent reaches) and
+// S(x_n); then it publishes the slot.  Wave 0 runs the recursion, one lane
+// per component: per element a 13-term row (the band against the
+// neighbours of lambda, exchanged through LDS) and the dL/dF term; the
+// next element's operands are loaded during the current one.  Wave 4 is
+// idle so the recursion's SIMD (waves are spread over the SIMDs in turn)
+// serves it alone.  Only the trajectory, g and the outputs touch HBM.  The
+// waits are between waves of one workgroup; they are bounded all the same,
+// and a wait that gives up stops the workgroup and leaves NaN in that
+// instance's gradients.
+constexpr int AP_NT = 512, AP_R = 24, AP_NB = 6;
+__device__ __forceinline__ int ap_builder(int wv) {
+  return wv >= 1 && wv <= 3 ? wv - 1 : (wv >= 5 ? wv - 2 : -1);
+}
+
+template <typename T, int D>
+struct AdjPipeSmem {
+  static constexpr int BW = DSysL96<T, D>::BW;
+  T band[AP_R][BW][D];  // band[s][r][j] = J(j - 4 + r, j) = J^T(j, j - 4 + r)
+  T g[AP_R][D];
+  T sens[AP_R][D];      // S(x_n)
+  StageL96<T, D> stage[AP_NB];
+  T zx[D + BW - 1];     // zx[q] = lambda[(q - 4) mod D]
+  int ready[AP_R];      // element index held by the slot (0: none yet)
+  int consumed;         // last element the recursion has finished
+  int abort_;
+};
+
+template <typename T, int D>
+__global__ __launch_bounds__(AP_NT) void k_adj_pipe_l96(AdjArgs a, T* dx0, T* dth, uint64_t lim) {
+  using S = DSysL96<T, D>;
+  constexpr int BW = S::BW, LO = S::BOFFT, R = AP_R;
+  static_assert(BW == 13 && LO == 4 && D <= PINT_WAVE, "Lorenz-96 band");
+  extern __shared__ __align__(16) unsigned char dyn[];
+  AdjPipeSmem<T, D>& sm = *reinterpret_cast<AdjPipeSmem<T, D>*>(dyn);
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  const int64_t inst = blockIdx.x;
+  const int64_t Tn = a.T;
+  const int j = lane < D ? lane : 0;  // lanes past D repeat lane 0
+  const T dt = (T)a.dt;
+  const T* G = static_cast<const T*>(a.g) + inst * Tn * D;
+  const T* X = static_cast<const T*>(a.traj) + inst * Tn * D;
+  const T* x0 = static_cast<const T*>(a.x0) + inst * D;
+  if (tid < R) sm.ready[tid] = 0;
+  if (tid == 0) {
+    sm.consumed = 0;
+    sm.abort_ = 0;
+  }
+  __syncthreads();
+  auto spin = [&](uint64_t& it) -> bool {  // true: stop
+    if (++it >= lim) {
+      __hip_atomic_store(&sm.abort_, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return __hip_atomic_load(&sm.abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+  };
+  auto ld = [](const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+  auto st = [](int* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+
+  const int e = ap_builder(wv);
+  if (e >= 0) {
+    // ------------------------------------------------------- builders ---
+    const T P[1] = {static_cast<const T*>(a.params)[inst * a.pstride]};
+    const T h2 = T(0.5) * dt, c6 = dt / T(6);
+    StageL96<T, D>* stg = &sm.stage[e];
+    auto fetch = [&](int64_t i, T& xv, T& gv) {  // x_n and g_n of element i (n = T - i)
+      const int64_t n = Tn - i;
+      xv = n == 0 ? x0[j] : X[(n - 1) * D + j];
+      gv = n == 0 ? T(0) : G[(n - 1) * D + j];
+    };
+    T xn = T(0), gn = T(0);
+    if (1 + e <= Tn) fetch(1 + e, xn, gn);
+    for (int64_t i = 1 + e; i <= Tn; i += AP_NB) {
+      const T xc = xn, gc = gn;
+      if (i + AP_NB <= Tn) fetch(i + AP_NB, xn, gn);  // the next element's loads fly meanwhile
+      uint64_t it = 0;
+      bool stop = false;
+      while (ld(&sm.consumed) < i - R)  // the slot's previous element is used
+        if ((stop = spin(it))) break;
+      if (stop) break;
+      const int slot = (int)(i % R);
+      T xs[1] = {lane < D ? xc : T(0)}, phi[1];
+      wave_rk4<T, S>(P, dt, xs, phi, stg, lane);
+      T col[BW];
+      S::jac_band_column(stg, j, dt, col);
+      // S = dPhi/dF through the stages (f_F = 1): D_1 = 1,
+      // D_s = Jf(y_s)(c D_{s-1}) + 1, S = dt/6 (D_1 + 2 D_2 + 2 D_3 + D_4)
+      T Dv = T(1), acc = T(1);
+#pragma unroll
+      for (int s = 1; s < 4; s++) {
+        const T c = (s == 3) ? dt : h2;
+        const T v = c * Dv;
+        const T* y = stg->x[s];
+        const T yp1 = y[j + 1 == D ? 0 : j + 1], ym1 = y[j == 0 ? D - 1 : j - 1];
+        const T ym2 = y[j >= 2 ? j - 2 : j + D - 2];
+        const T vp1 = __shfl(v, (j + 1) % D, PINT_WAVE), vm1 = __shfl(v, (j + D - 1) % D, PINT_WAVE);
+        const T vm2 = __shfl(v, (j + D - 2) % D, PINT_WAVE);
+        Dv = ym1 * (vp1 - vm2) + (yp1 - ym2) * vm1 - v + T(1);
+        acc += ((s == 3) ? T(1) : T(2)) * Dv;
+      }
+      if (lane < D) {
+#pragma unroll
+        for (int r = 0; r < BW; r++) sm.band[slot][r][lane] = col[r];
+        sm.g[slot][lane] = gc;
+        sm.sens[slot][lane] = c6 * acc;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) st(&sm.ready[slot], (int)i);
+    }
+  } else if (wv == 0) {
+    // ------------------------------------------------------ recursion ---
+    __builtin_amdgcn_s_setprio(3);
+    T z = Tn > 0 ? G[(Tn - 1) * D + j] : T(0);  // lambda_T = g_T
+    T th = T(0);
+    auto put_z = [&](T v) {  // zx[q] = lambda[(q - 4) mod D]
+      if (lane < D) {
+        sm.zx[lane + LO] = v;
+        if (lane >= D - LO) sm.zx[lane + LO - D] = v;
+        if (lane < BW - 1 - LO) sm.zx[lane + LO + D] = v;
+      }
+    };
+    put_z(z);
+    T zv[BW], bA[BW], bB[BW], gA = T(0), gB = T(0), sA = T(0), sB = T(0);
+    bool stop = false;
+    auto wait_el = [&](int64_t i) -> bool {  // true: element i is in its slot
+      uint64_t it = 0;
+      while (ld(&sm.ready[i % R]) != (int)i)
+        if (spin(it)) return false;
+      return true;
+    };
+    auto load_el = [&](int64_t i, T (&bv)[BW], T& gv, T& sv) {
+      const int slot = (int)(i % R);
+#pragma unroll
+      for (int r = 0; r < BW; r++) bv[r] = sm.band[slot][r][j];
+      gv = sm.g[slot][j];
+      sv = sm.sens[slot][j];
+    };
+    if (Tn > 0) {
+      stop = !wait_el(1);
+      if (!stop) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+        for (int r = 0; r < BW; r++) zv[r] = sm.zx[j + r];
+        load_el(1, bA, gA, sA);
+      }
+    }
+    int nxt = Tn > 1 ? ld(&sm.ready[2 % R]) : 0;  // flag of the next element, read ahead
+    // element i with operands (bc, gc, sc); the next one's go to (bn, gn, sn)
+    auto step = [&](int64_t i, T (&bc)[BW], T& gc, T& sc, T (&bn)[BW], T& gn, T& sn)
+        __attribute__((always_inline)) -> bool {
+      const bool more = i < Tn;
+      if (more) {
+        if (nxt != (int)(i + 1)) {
+          if (!wait_el(i + 1)) return false;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        load_el(i + 1, bn, gn, sn);
+        nxt = i + 2 <= Tn ? ld(&sm.ready[(i + 2) % R]) : 0;
+      }
+      th += sc * z;  // S(x_n) . lambda_{n+1}
+      z = band_row13<T>(gc, bc, zv);
+      put_z(z);
+      if (more) {
+#pragma unroll
+        for (int r = 0; r < BW; r++) zv[r] = sm.zx[j + r];
+      }
+      st(&sm.consumed, (int)i);
+      return more;
+    };
+    if (!stop) {
+      for (int64_t i = 1;;) {
+        bool go = step(i, bA, gA, sA, bB, gB, sB);
+        if (!go) break;
+        i++;
+        go = step(i, bB, gB, sB, bA, gA, sA);
+        if (!go) break;
+        i++;
+      }
+    }
+    stop = ld(&sm.abort_) != 0;
+    th = wave_sum(lane < D ? th : T(0));
+    const T nan = T(__builtin_nan(""));
+    if (lane < D) dx0[inst * D + lane] = stop ? nan : z;
+    if (lane == 0 && dth) dth[inst] = stop ? nan : th;
+  }
+}
+
 // ------------------------------------------------------------- host -------
 
 template <typename F>
@@ -348,8 +547,28 @@ static AdjLayout adj_layout(int system, int d, int64_t B, int64_t T, int64_t seg
   return l;
 }
 
+// Lorenz-96 d = 40 takes the fused reverse pass (k_adj_pipe_l96) unless the
+// pipelined kernels are switched off (pint_set_dense_pipeline).
+static bool adj_fused(int system, int d) { return system == 5 && d == 40 && dense_pipeline(); }
+
+template <typename T>
+static int adj_pipe_launch(const AdjArgs& a, void* dL_dx0, void* dL_dth, hipStream_t st) {
+  using SM = AdjPipeSmem<T, 40>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adj_pipe_l96<T, 40>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(SM)) != hipSuccess)
+      return ST_DEVICE;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_adj_pipe_l96<T, 40>), dim3((unsigned)a.B), dim3(AP_NT), sizeof(SM), st, a,
+                     static_cast<T*>(dL_dx0), static_cast<T*>(dL_dth), wait_limit());
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
+}
+
 size_t adjoint_ws_bytes(int system, int d, int64_t B, int64_t T, int64_t seg, int dtype) {
   if (!small_supported(system, d) && !dense_supported(system, d)) return 0;
+  if (adj_fused(system, d)) return 256;  // no elements, no lambda: nothing beyond the call's outputs
   return adj_layout(system, d, B, T, seg, dtype).total;
 }
 
@@ -357,6 +576,27 @@ int adjoint(const SolveArgs& sa, const void* g, void* dL_dx0, void* dL_dth, int6
   const int d = sa.d;
   const int64_t B = sa.B, T = sa.T_uniform, T1 = T + 1;
   if (sa.system == 6 && dL_dth) return ST_UNSUPPORTED;  // Kuramoto: dL/dx0 only
+  if (adj_fused(sa.system, d)) {
+    if (!sa.ws || sa.ws_bytes < 256) return ST_WORKSPACE;
+    if (T == 0) {
+      if (dL_dth)
+        if (int rc = fill_u32(static_cast<uint32_t*>(dL_dth), (size_t)B * (sa.dtype == 0 ? 2 : 1), 0u, sa.stream))
+          return rc;
+      return fill_u32(static_cast<uint32_t*>(dL_dx0), (size_t)B * d * (sa.dtype == 0 ? 2 : 1), 0u, sa.stream);
+    }
+    AdjArgs a{};
+    a.B = B;
+    a.T = T;
+    a.x0 = sa.x0;
+    a.params = sa.params;
+    a.pstride = sa.pstride;
+    a.traj = sa.traj;
+    a.g = g;
+    a.dt = sa.dt;
+    if (sa.dtype == 0) return adj_pipe_launch<double>(a, dL_dx0, dL_dth, sa.stream);
+    if (sa.dtype == 1) return adj_pipe_launch<float>(a, dL_dx0, dL_dth, sa.stream);
+    return ST_UNSUPPORTED;
+  }
   const AdjLayout lay = adj_layout(sa.system, d, B, T, seg, sa.dtype);
   if (!sa.ws || sa.ws_bytes < lay.total) return ST_WORKSPACE;
   char* w = static_cast<char*>(sa.ws);
