@@ -24,6 +24,22 @@ __device__ __forceinline__ double acc_norm(double m, T v) {
   return a > m ? a : m;
 }
 
+// Sum over the 64 lanes of two values at once, every lane getting the same
+// bits: DPP butterflies inside each row of 16 lanes (quad swaps, then the
+// half-row and row mirrors), then the four row sums read from lanes 0, 16,
+// 32, 48 and added in a fixed order.  No LDS round trip.
+constexpr int DPP_ROW_MIRROR = 0x140;       // lane i <- lane 15 - i within its row
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane i <- lane 7 - i within its half row
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <typename T>
+__device__ __forceinline__ void wave_sum2_dpp(T& a, T& b);
+
 // ---------------------------------------------------- wave / block reduce --
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -217,6 +233,20 @@ __device__ __forceinline__ void block_scan_aff(Aff<T, D>& e, Aff<T, D>* lds) {
     aff_after(e, c);
   }
   if constexpr (LDS_ONLY) lds_barrier(); else __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_sum2_dpp(T& a, T& b) {
+  a += dpp_xor1(a);
+  b += dpp_xor1(b);
+  a += dpp_xor2(a);
+  b += dpp_xor2(b);
+  a += dpp_row<DPP_ROW_HALF_MIRROR, 0xf>(T(0), a);
+  b += dpp_row<DPP_ROW_HALF_MIRROR, 0xf>(T(0), b);
+  a += dpp_row<DPP_ROW_MIRROR, 0xf>(T(0), a);
+  b += dpp_row<DPP_ROW_MIRROR, 0xf>(T(0), b);
+  a = (read_lane(a, 0) + read_lane(a, 16)) + (read_lane(a, 32) + read_lane(a, 48));
+  b = (read_lane(b, 0) + read_lane(b, 16)) + (read_lane(b, 32) + read_lane(b, 48));
 }
 
 // ---------------------------------------------------------------- atomics --

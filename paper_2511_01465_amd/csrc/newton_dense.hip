@@ -154,6 +154,32 @@ __device__ __forceinline__ void dn_elements(DenseSmem<T, S>& sm, T dt, const T* 
   constexpr int D = S::D, NT = S::NT, NW = NT / PINT_WAVE;
   constexpr int SPP = ElemShape<S>::SPP, JT = ElemShape<S>::JT;
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  if constexpr (S::MATFREE) {
+    // a wave per step: the RK4 step stores its stage record straight into
+    // the element slot (the fold applies J from it), and b
+    for (int64_t m = m_first + (int64_t)wv * m_stride; m < len; m += (int64_t)NW * m_stride) {
+      const int64_t n = lo + m;
+      T xp[S::R], xc[S::R], phi[S::R];
+      wave_load<T, S>(X, sm.x0, n - 1, xp, lane);
+      wave_load<T, S>(X, sm.x0, n, xc, lane);
+      wave_rk4<T, S>(sm.P, dt, xp, phi, reinterpret_cast<typename S::Stage*>(AT + m * S::STAGE_SCALARS), lane);
+      double hm = 0.0;
+#pragma unroll
+      for (int r = 0; r < S::R; r++) {
+        const int i = lane + 64 * r;
+        if (i < D) {
+          bb[m * D + i] = phi[r] - xc[r];
+          hm = acc_norm(hm, xc[r] - phi[r]);
+        }
+      }
+      if (hn) {
+        hm = wave_max(hm);
+        if (lane == 0) hn[m] = hm;
+      }
+    }
+    __syncthreads();
+    return;
+  }
   for (int64_t g0 = m_first; g0 < len; g0 += m_stride * SPP) {
     for (int sl = wv; sl < SPP; sl += NW) {
       const int64_t m = g0 + sl * m_stride;
@@ -303,12 +329,34 @@ struct BandShape {
   static constexpr int PER = NB + 2 * S::D;          // per step: band, b, old x
 };
 
+// Matrix-free systems: per step the stage record, b and the old state.
+template <class S>
+struct MfShape {
+  static constexpr int CH = 6;                       // steps per chunk
+  static constexpr int SP = S::STAGE_SCALARS;        // stage record scalars
+  static constexpr int PER = SP + 2 * S::D;
+};
+
+// Dynamic LDS of the folding workgroup: two chunks of staged steps.
 template <typename T, class S>
-constexpr size_t band_lds_bytes() {
+constexpr size_t fold_lds_bytes() {
   if constexpr (S::BANDED)
     return 2 * (size_t)BandShape<S>::CH * BandShape<S>::PER * sizeof(T);
+  else if constexpr (S::MATFREE)
+    return 2 * (size_t)MfShape<S>::CH * MfShape<S>::PER * sizeof(T);
   else
     return 0;
+}
+
+// Scalars per stored window element: the band, the stage record, or J.
+template <class S>
+constexpr int64_t elem_scalars() {
+  if constexpr (S::BANDED)
+    return (int64_t)S::BW * S::D;
+  else if constexpr (S::MATFREE)
+    return S::STAGE_SCALARS;
+  else
+    return (int64_t)S::D * S::D;
 }
 
 // Copy n consecutive scalars from global src to LDS dst with threads
@@ -542,6 +590,110 @@ __device__ __forceinline__ int64_t dn_fold_band(DenseSmem<T, S>& sm, T* lbuf, co
   return q == INT64_MAX ? len : q;
 }
 
+// Matrix-free systems (Kuramoto): the window's Newton step with J applied
+// through the RK4 tangent from each step's stage record,
+//   u_1 = v, K_s = J_f(y_s) u_s, u_{s+1} = v + c_s K_s,
+//   J v = v + dt/6 (K_1 + 2 K_2 + 2 K_3 + K_4),
+// J_f(y) u = K (c (c.u) + s (s.u)) - K (c C + s S) u — the same chain the
+// dense Jacobian columns follow, applied to dx_{m-1} instead of to the unit
+// vectors.  Wave 0 folds, two components per lane, the two dot products of
+// a stage as one DPP wave sum; waves 1.. stage the next chunk of records
+// through LDS meanwhile, as in the banded fold.
+template <typename T, class S>
+__device__ __forceinline__ int64_t dn_fold_mf(DenseSmem<T, S>& sm, T* lbuf, const T* St, const T* bb,
+                                              const T* Xw, T* xnb, int64_t len, bool plain, double guard,
+                                              T dt) {
+  constexpr int D = S::D, NT = S::NT;
+  using MS = MfShape<S>;
+  constexpr int CH = MS::CH, SP = MS::SP, PER = MS::PER;
+  constexpr int R = D / PINT_WAVE;  // components per lane of wave 0
+  static_assert(D % PINT_WAVE == 0 && NT > PINT_WAVE, "whole lanes of wave 0");
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  const int nl = NT - PINT_WAVE, lt = tid - PINT_WAVE;
+  constexpr int V = 16 / sizeof(T), NL = NT - PINT_WAVE;
+  constexpr int MVS = (CH * SP / V + NL - 1) / NL, MVX = (CH * D / V + NL - 1) / NL;
+  auto load = [&](int64_t c0, int n, int h) {
+    T* dst = lbuf + (size_t)h * CH * PER;
+    lds_copy3<T, MVS, MVX>(dst, St + c0 * SP, n * SP, dst + CH * SP, bb + c0 * D, n * D,
+                           dst + CH * SP + CH * D, Xw + c0 * D, n * D, lt, nl);
+  };
+  const int64_t nch = (len + CH - 1) / CH;
+  if (wv > 0 && len > 0) load(0, (int)(len < CH ? len : CH), 0);
+  lds_barrier();
+  int64_t bad = INT64_MAX;
+  const T h2 = T(0.5) * dt, c6 = dt / T(6), Kc = sm.P[0];
+  T v[R];  // dx_{m-1}, components lane + 64 r
+#pragma unroll
+  for (int r = 0; r < R; r++) v[r] = T(0);
+  for (int64_t c = 0; c < nch; c++) {
+    const int64_t c0 = c * CH;
+    const int n = (int)((len - c0) < CH ? (len - c0) : CH);
+    if (wv > 0) {
+      if (c + 1 < nch) {
+        const int64_t c1 = c0 + CH;
+        load(c1, (int)((len - c1) < CH ? (len - c1) : CH), (int)((c + 1) & 1));
+      }
+    } else if (bad == INT64_MAX) {
+      const T* L = lbuf + (size_t)(c & 1) * CH * PER;
+      for (int m = 0; m < n; m++) {
+        const T* rec = L + m * SP;  // c[4][D], s[4][D], C[4], S[4]
+        T z[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) z[r] = L[CH * SP + m * D + lane + PINT_WAVE * r];
+        if (c0 + m > 0) {
+          T u[R], acc[R];
+#pragma unroll
+          for (int r = 0; r < R; r++) u[r] = v[r];
+#pragma unroll
+          for (int s = 0; s < 4; s++) {
+            T cs[R], sn[R];
+            T pa = T(0), pb = T(0);
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+              cs[r] = rec[s * D + lane + PINT_WAVE * r];
+              sn[r] = rec[4 * D + s * D + lane + PINT_WAVE * r];
+              pa += cs[r] * u[r];
+              pb += sn[r] * u[r];
+            }
+            const T C = rec[8 * D + s], Sg = rec[8 * D + 4 + s];
+            wave_sum2_dpp(pa, pb);
+            const T w = (s == 0 || s == 3) ? T(1) : T(2);
+            const T cc = (s == 2) ? dt : h2;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+              const T K = Kc * (cs[r] * pa + sn[r] * pb) - Kc * (cs[r] * C + sn[r] * Sg) * u[r];
+              acc[r] = (s == 0) ? K : acc[r] + w * K;
+              u[r] = v[r] + cc * K;
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < R; r++) z[r] = (v[r] + c6 * acc[r]) + z[r];
+        }
+        bool badm = false;
+        T xn[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          v[r] = z[r];
+          xn[r] = L[CH * SP + CH * D + m * D + lane + PINT_WAVE * r] + z[r];
+          badm = badm || !finite_(xn[r]) || fabs((double)xn[r]) > guard;
+        }
+        if (!plain && badm) bad = c0 + m;
+        // the first cut step ends the fold; it and later steps stay unwritten
+        if (!plain && __ballot(bad != INT64_MAX)) break;
+#pragma unroll
+        for (int r = 0; r < R; r++) xnb[(c0 + m) * D + lane + PINT_WAVE * r] = xn[r];
+      }
+      bad = wave_min_i64(bad);
+    }
+    lds_barrier();  // chunk c+1 staged, chunk c folded
+  }
+  if (tid == 0) sm.redi[0] = bad;
+  __syncthreads();  // also: wave 0's updated states are visible to the commit
+  const int64_t q = sm.redi[0];
+  __syncthreads();
+  return q == INT64_MAX ? len : q;
+}
+
 // Write the accepted part [0, q) of the updated window states.
 template <typename T, class S>
 __device__ __forceinline__ void dn_commit(T* Xw, const T* xnb, int64_t q) {
@@ -565,7 +717,7 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense(DenseKArgs a) {
   __shared__ DenseSmem<T, S> sm;
   __shared__ uint32_t s_slot;
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  T* band_buf = reinterpret_cast<T*>(dyn_lds);  // band_lds_bytes<T, S>() bytes
+  T* band_buf = reinterpret_cast<T*>(dyn_lds);  // fold_lds_bytes<T, S>() bytes
   const int tid = threadIdx.x;
   const T dt = (T)a.dt;
   T* slot = static_cast<T*>(a.ws_elems) + (int64_t)blockIdx.x * a.slot_stride;
@@ -615,6 +767,8 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense(DenseKArgs a) {
       if constexpr (S::BANDED)
         // the accepted states go straight into the trajectory
         q = dn_fold_band<T, S>(sm, band_buf, AT, bb, X + (lo - 1) * D, X + (lo - 1) * D, len, plain, a.guard);
+      else if constexpr (S::MATFREE)
+        q = dn_fold_mf<T, S>(sm, band_buf, AT, bb, X + (lo - 1) * D, dxb, len, plain, a.guard, dt);
       else
         q = dn_fold<T, S>(sm, AT, bb, X + (lo - 1) * D, dxb, len, plain, a.guard);
       if constexpr (!S::BANDED) dn_commit<T, S>(X + (lo - 1) * D, dxb, q);
@@ -709,7 +863,7 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
   __shared__ DenseSmem<T, S> sm;
   __shared__ int64_t s_win[2];
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  T* band_buf = reinterpret_cast<T*>(dyn_lds);  // band_lds_bytes<T, S>() bytes
+  T* band_buf = reinterpret_cast<T*>(dyn_lds);  // fold_lds_bytes<T, S>() bytes
   __shared__ int32_t s_done;
   const int tid = threadIdx.x;
   const int64_t inst = blockIdx.x / G;
@@ -857,12 +1011,15 @@ __global__ __launch_bounds__(S::NT) void k_newton_dense_coop(DenseKArgs a, int G
       if (fold) {
         const int64_t len = ((W >= Tn - p + 1) ? Tn : p + W - 1) - p + 1;
         const int64_t off = p - base;
-        constexpr int64_t ES = S::BANDED ? (int64_t)S::BW * D : (int64_t)D * D;  // scalars per element
+        constexpr int64_t ES = elem_scalars<S>();  // scalars per element
         int64_t q;
         if constexpr (S::BANDED)
           // the accepted states go straight into the trajectory
           q = dn_fold_band<T, S>(sm, band_buf, AT + off * ES, bb + off * D, X + (p - 1) * D, X + (p - 1) * D,
                                  len, false, a.guard);
+        else if constexpr (S::MATFREE)
+          q = dn_fold_mf<T, S>(sm, band_buf, AT + off * ES, bb + off * D, X + (p - 1) * D, dxb, len, false,
+                               a.guard, dt);
         else
           q = dn_fold<T, S>(sm, AT + off * ES, bb + off * D, X + (p - 1) * D, dxb, len, false, a.guard);
         if constexpr (!S::BANDED) dn_commit<T, S>(X + (p - 1) * D, dxb, q);
@@ -1091,7 +1248,7 @@ static int coop_groups(const SolveArgs& a) {
   if (G > 64) G = 64;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_newton_dense_coop<T, S>, S::NT,
-                                                   band_lds_bytes<T, S>()) != hipSuccess)
+                                                   fold_lds_bytes<T, S>()) != hipSuccess)
     return 1;
   const int64_t cap = (int64_t)per_cu * num_cus();
   while (G > 1 && a.B * G > cap) G--;
@@ -1148,7 +1305,7 @@ int dense_solve(const SolveArgs& a) {
     CoopCtl* ctl = reinterpret_cast<CoopCtl*>(w + l.ctl_off);
     // queue counter and control blocks start at zero (a kernel, not a memset)
     if (int rc = fill_u32(reinterpret_cast<uint32_t*>(w), l.slots_off / 4, 0u, a.stream)) return rc;
-    const size_t lds = band_lds_bytes<T, S>();
+    const size_t lds = fold_lds_bytes<T, S>();
     static bool attr_set = false;  // per (T, S) instantiation
     if (!attr_set && lds > 0) {
       if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_newton_dense_coop<T, S>),

@@ -60,6 +60,7 @@ struct DSysL96 {
   // is exactly zero.  Band storage: diagonal k = (j - i + BOFF) mod D,
   // k < BW, at band[k * D + i].
   static constexpr bool BANDED = true;
+  static constexpr bool MATFREE = false;
   static constexpr int BW = 13, BOFF = 8;
   static_assert(D >= 2 * BW, "band must not wrap onto itself");
 
@@ -240,6 +241,14 @@ struct DSysKur {
   static_assert(D % 64 == 0 && D % QB == 0, "Kuramoto dense path: d a multiple of 64");
   static constexpr bool BANDED = false;  // all-to-all coupling: J is dense
   static constexpr int BW = 0, BOFF = 0;
+  // Inside the solvers J is applied without being formed: J_f(y) w =
+  // K (c (c.w) + s (s.w)) - K (c C + s S) w costs two dot products over d
+  // and O(d) work, so J v goes through the four RK4 stages (tangent) from
+  // the stage data alone (cos, sin and their sums at the stage points:
+  // STAGE_SCALARS values per step instead of d^2).
+  static constexpr bool MATFREE = true;
+  static constexpr int STAGE_SCALARS = 8 * D + 8;
+  static_assert(sizeof(StageKur<T, D>) == STAGE_SCALARS * sizeof(T), "stage record layout");
 
   __device__ static void sums(const T (&x)[R], T (&sn)[R], T (&cs)[R], T& S, T& C, int lane) {
     T ls = T(0), lc = T(0);
