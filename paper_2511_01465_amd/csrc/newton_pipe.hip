@@ -23,8 +23,9 @@
 //   wave 0 (fold)     evaluates the residuals from the ring to find p_u,
 //                     then folds dx_n = J_{n-1} dx_{n-1} - h_n over the
 //                     window, each updated state into an LDS output ring;
-//   wave 2 (writer)   writes the updated states into the trajectory and
-//                     publishes how far iterate u is final.
+//   wave 2 (writer)   checks each updated state against the guard, writes
+//                     it into the trajectory and publishes how far iterate
+//                     u is final; the first state that fails is the cut.
 // Only states cross between agents: written with device-scope atomic stores
 // (the trajectory is updated in place), announced by a per-agent progress
 // word stored after the writes complete.  A state of iterate u-1 is final
@@ -63,10 +64,10 @@ constexpr unsigned long long DONE_BIT = 1ull << 63;
 // elements (one of them alone on its SIMD, the others beside the light
 // loader and writer).  Two waves per SIMD leave each up to 256 registers.
 constexpr int PIPE_NT = 512;
-constexpr int PIPE_NE = 4;
+constexpr int PIPE_NE = 5;
 __device__ __forceinline__ int pipe_elem_index(int wv) {
-  // waves 3, 5, 6, 7 -> 0..3; -1 for the others
-  return wv == 3 ? 0 : (wv >= 5 && wv <= 7) ? wv - 4 : -1;
+  // waves 3..7 -> 0..4; -1 for the others
+  return wv >= 3 ? wv - 3 : -1;
 }
 constexpr int PIPE_R = 24;      // ring slots (steps)
 
@@ -99,12 +100,12 @@ struct PipeSmem {
   T P[S::NP], x0[D];
   double red[PIPE_NT / PINT_WAVE];
   int staged[R], ready[R];
-  int f_pos;       // last step the fold (or its search) has completed
-  int out_ready;   // last step whose updated state is in xo
+  int f_pos;       // last step the fold (or its search) has completed; in the
+                   // fold, also the last step whose updated state is in xo
   int written;     // last step the writer has taken from xo
   int pprev;       // p_{u-1}; 0 until known
   int p_u, e_u;    // this update's window; 0 until known
-  int fold_end;    // -1 while folding; else the last accepted step (p_u - 1: none)
+  int fold_end;    // -1 until the writer has published the update; then its last accepted step
   int abort_;      // this agent stops (the iteration ended, or a wait gave up)
 };
 
@@ -223,7 +224,6 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
         sm.ready[r] = -1;
       }
       sm.f_pos = -1;
-      sm.out_ready = -1;
       sm.written = -1;
       sm.pprev = 0;
       sm.p_u = 0;
@@ -263,6 +263,13 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
       }
       int64_t final_upto = u >= 2 ? pprev - 1 : Tn;
       int64_t m = pprev - 1;
+      // how far iterate u-1 is final, from a progress word of update u-1
+      auto take_prog = [&](unsigned long long pr) {
+        const int64_t tag = (int64_t)(pr >> 32);
+        if (tag > u - 1) final_upto = Tn;
+        else if (tag == u - 1 && (int64_t)(pr & 0xffffffffull) > final_upto) final_upto = (int64_t)(pr & 0xffffffffull);
+      };
+      uint32_t polls = 0;
       while (!lds_ld(&sm.abort_) && lds_ld(&sm.fold_end) < 0 && m <= Tn) {
         const int e_u = lds_ld(&sm.e_u);
         int64_t lim_m = (int64_t)lds_ld(&sm.f_pos) + R - 1;  // ring space
@@ -273,12 +280,11 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
           continue;
         }
         if (m > final_upto && m <= eprev) {
-          const unsigned long long pr = gld(&rec[aprev].prog);
-          const int64_t tag = (int64_t)(pr >> 32);
-          if (tag > u - 1) final_upto = Tn;
-          else if (tag == u - 1) final_upto = (int64_t)(pr & 0xffffffffull);
+          take_prog(gld(&rec[aprev].prog));
           if (m > final_upto) {
-            if (pipe_stop(c, u)) {
+            // whether the iteration ended before update u-1 (then no more
+            // progress comes) is checked now and then, off the poll's path
+            if ((++polls & 31) == 0 && pipe_stop(c, u)) {
               lds_st(&sm.abort_, 1);
               break;
             }
@@ -312,64 +318,100 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
       __builtin_amdgcn_s_setprio(0);
     } else if (wv == 2) {
       // ------------------------------------------------------- writer ---
+      // Publishes the window start, then takes the updated states from xo
+      // in order: each is checked against the guard (finite, within
+      // `guard`) before it is stored, so the first state that fails is the
+      // cut and nothing from it on is published.  The writer then records
+      // the last accepted step (fold_end), which ends the update's roles.
       __builtin_amdgcn_s_setprio(2);
       uint64_t it = 0;
       int p = 0;
-      while (!lds_ld(&sm.abort_) && (p = lds_ld(&sm.p_u)) == 0 && lds_ld(&sm.fold_end) < 0)
+      while (!lds_ld(&sm.abort_) && (p = lds_ld(&sm.p_u)) == 0)
         if (spin(it)) break;
       if (p > 0 && !lds_ld(&sm.abort_)) {
         wg_acquire();
         const int e = lds_ld(&sm.e_u);
+        const int i = lane < D ? lane : 0;
         if (lane == 0) {
           gst(&rec[g].start, ((unsigned long long)u << 32) | (unsigned)p);
           wait_stores();
           gst(&rec[g].prog, ((unsigned long long)u << 32) | (unsigned)(p - 1));
         }
-        int w = p - 1;
+        int w = p - 1, fe = -1;
         it = 0;
         for (;;) {
-          const int avail = lds_ld(&sm.out_ready);
+          const int avail = lds_ld(&sm.f_pos);  // steps up to avail are in xo
           if (avail > w) {
             wg_acquire();
-            for (int n = w + 1; n <= avail; n++)
-              if (lane < D) pst(X + (int64_t)(n - 1) * D + lane, sm.xo[n % R][lane]);
+            // up to 8 states at a time: all their LDS reads in flight, then
+            // each checked and stored in order
+            const int hi = avail - w > 8 ? w + 8 : avail;
+            T v[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++)
+              if (w + 1 + j <= hi) v[j] = sm.xo[(w + 1 + j) % R][i];
+            int n = w + 1;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+              if (n > hi) break;
+              if (__ballot(lane < D && (!finite_(v[j]) || fabs((double)v[j]) > a.guard))) break;
+              if (lane < D) pst(X + (int64_t)(n - 1) * D + lane, v[j]);
+              n++;
+            }
+            const int last = n - 1;
             // the xo slots are read (the stores hold the values)
             asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-            if (lane == 0) lds_st(&sm.written, avail);
+            if (lane == 0) lds_st(&sm.written, last);
             wait_stores();
-            if (lane == 0) gst(&rec[g].prog, ((unsigned long long)u << 32) | (unsigned)avail);
-            w = avail;
+            if (lane == 0 && last > w) gst(&rec[g].prog, ((unsigned long long)u << 32) | (unsigned)last);
+            w = last;
             it = 0;
+            if (n <= hi) {  // state n fails the guard: the cut
+              fe = n - 1;
+              break;
+            }
+            if (w >= e) {
+              fe = e;
+              break;
+            }
             continue;
           }
-          const int fe = lds_ld(&sm.fold_end);
-          if (fe >= 0 && w >= fe) break;
           if (lds_ld(&sm.abort_)) break;
           if (spin(it)) break;
         }
-        if (!lds_ld(&sm.abort_)) {
-          const int fe = lds_ld(&sm.fold_end);
-          if (fe < e && u >= 2) {
-            // cut at fe + 1: iterate u equals iterate u-1 on (fe, e]; wait
-            // until that is final before declaring iterate u final
-            it = 0;
-            for (;;) {
-              const unsigned long long pr = gld(&rec[aprev].prog);
-              const int64_t tag = (int64_t)(pr >> 32);
-              if (tag > u - 1 || (tag == u - 1 && (int64_t)(pr & 0xffffffffull) >= e)) break;
-              // beyond the previous window the states are the initial iterate
-              const unsigned long long s = gld(&rec[aprev].start);
-              const int64_t pp = (int64_t)(s & 0xffffffffull);
-              if ((int64_t)(s >> 32) == u - 1 && ((W >= Tn - pp + 1) ? Tn : pp + W - 1) < fe + 1) break;
-              if (pipe_stop(c, u)) {
-                lds_st(&sm.abort_, 1);
-                break;
-              }
-              if (spin(it)) break;
+        if (fe >= 0 && !lds_ld(&sm.abort_)) {
+          if (fe == p - 1) {  // the first updated state is unusable
+            if (lane == 0) {
+              pipe_finish(c, ST_NONFINITE, u - 1);
+              lds_st(&sm.abort_, 1);
             }
+          } else {
+            if (lane == 0) {
+              wg_release();
+              lds_st(&sm.fold_end, fe);
+            }
+            if (fe < e && u >= 2) {
+              // cut at fe + 1: iterate u equals iterate u-1 on (fe, e]; wait
+              // until that is final before declaring iterate u final
+              it = 0;
+              for (;;) {
+                const unsigned long long pr = gld(&rec[aprev].prog);
+                const int64_t tag = (int64_t)(pr >> 32);
+                if (tag > u - 1 || (tag == u - 1 && (int64_t)(pr & 0xffffffffull) >= e)) break;
+                // beyond the previous window the states are the initial iterate
+                const unsigned long long s0 = gld(&rec[aprev].start);
+                const int64_t pp = (int64_t)(s0 & 0xffffffffull);
+                if ((int64_t)(s0 >> 32) == u - 1 && ((W >= Tn - pp + 1) ? Tn : pp + W - 1) < fe + 1) break;
+                if (pipe_stop(c, u)) {
+                  lds_st(&sm.abort_, 1);
+                  break;
+                }
+                if (spin(it)) break;
+              }
+            }
+            if (lane == 0 && !lds_ld(&sm.abort_))
+              gst(&rec[g].prog, ((unsigned long long)u << 32) | (unsigned long long)Tn);
           }
-          if (lane == 0 && !lds_ld(&sm.abort_))
-            gst(&rec[g].prog, ((unsigned long long)u << 32) | (unsigned long long)Tn);
         }
       }
       __builtin_amdgcn_s_setprio(0);
@@ -380,7 +422,7 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
       int pprev = 0;
       while ((pprev = lds_ld(&sm.pprev)) == 0)
         if (spin(it)) break;
-      const int i = lane < D ? lane : 0;
+      const int i = lane < D ? lane : 0;  // lanes past D repeat lane 0
       const int tn = (int)Tn;
       bool stop = lds_ld(&sm.abort_) != 0 || pprev == 0;
       // Ring slots of steps n-1 and n, advanced with n (no divisions).
@@ -393,12 +435,14 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
       };
       // Wait for element n-1 and state n (and, in the fold, for the writer
       // to have taken the output slot's previous occupant n - R when that
-      // was a step of this update): the three flags are read together.
+      // was a step of this update): the three flags are read together.  In
+      // the fold the wait also ends when the writer has cut the update.
       auto await = [&](int xo_from) -> bool {
         uint64_t w = 0;
         for (;;) {
           const int fr = lds_ld(&sm.ready[sp]), fs = lds_ld(&sm.staged[sc]), fw = lds_ld(&sm.written);
           if ((fr == n - 1) & (fs == n) & (xo_from == 0 || n - R < xo_from || fw >= n - R)) break;
+          if (xo_from != 0 && lds_ld(&sm.fold_end) >= 0) return false;
           if (spin(w)) return false;
         }
         wg_acquire();
@@ -444,75 +488,94 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
           wg_release();
           lds_st(&sm.p_u, p);
         }
-        // dx_p = -h_p, then dx_n = J(x_{n-1}) dx_{n-1} - h_n.  Software
-        // pipelined: the operands of step n+1 (its band row, Phi(x_n),
-        // x_{n+1} and the neighbours of dx_n) are loaded during step n, as
-        // soon as dx_n is written and step n+1's flags (read at the start of
-        // step n) show them in the ring.
-        T dx = -h;
-        int last = p - 1;
-        T bv[BW], zv[BW], phc = T(0), xc = sm.sx[sc][i];
-        auto load_ops = [&]() {  // operands of step n from slots sp (element n-1) and sc (state n)
-          // the neighbours of dx first: they are the step's critical path
-#pragma unroll
-          for (int k = 0; k < BW; k++) zv[k] = sm.zx[i + k];
-          const T* band = sm.sband[sp];
-#pragma unroll
-          for (int k = 0; k < BW; k++) bv[k] = band[k * D + i];
-          phc = sm.sphi[sp][i];
-          xc = sm.sx[sc][i];
+        // dx_p = -h_p, then dx_n = J(x_{n-1}) dx_{n-1} - h_n.  Only
+        // register dependences wait: one wave's LDS operations are
+        // performed in issue order, so dx_n's neighbours are read right
+        // after they are written, and a step's updated state and its f_pos
+        // store need no fence between them (the writer reads f_pos, then
+        // the slot).  A step issues the next step's operand loads (band row,
+        // Phi(x_n), x_{n+1}, checked ready by flags read a step earlier)
+        // before its own row sum, and the reads of dx_n's neighbours right
+        // after the writes.  The guard is the writer's.
+        auto cbar = [] { asm volatile("" ::: "memory"); };
+        // every lane writes dx twice: at zx[i + BOFF], and at its wrap-around
+        // copy (rows D-BOFF.. and 0..BW-BOFF-2) or else a spare slot
+        const int zw2 = (i >= D - BOFF) ? i + BOFF - D : (i + BOFF + D < D + BW - 1 ? i + BOFF + D : 2 * D - 1);
+        static_assert(D + BW - 1 < 2 * D - 1, "spare zx slot");
+        auto put = [&](T dxn, T xn) {
+          sm.zx[i + BOFF] = dxn;
+          sm.zx[zw2] = dxn;
+          sm.xo[sc][i] = xn;
         };
-        for (;;) {
-          // step n+1's flags, read now, checked once dx_n is written
-          const int sn = sc + 1 == R ? 0 : sc + 1;
-          const int fr1 = lds_ld(&sm.ready[sc]), fs1 = lds_ld(&sm.staged[sn]), fw1 = lds_ld(&sm.written);
-          if (n > p) dx = band_row13<T>(phc - xc, bv, zv);
-          const T xn = xc + dx;
-          if (lane < D) {  // dx_n for the next step, with the wrap-around copies
-            sm.zx[i + BOFF] = dx;
-            if (i >= D - BOFF) sm.zx[i + BOFF - D] = dx;
-            if (i + BOFF + D < D + BW - 1) sm.zx[i + BOFF + D] = dx;
-          }
-          const bool more = n < e;
-          const bool next_ready =
-              more && (fr1 == n) & (fs1 == n + 1) & (n + 1 - R < p || fw1 >= n + 1 - R);
-          const int sp0 = sp, sc0 = sc;
-          if (next_ready) {
-            wg_acquire();
-            sp = sc;  // (advance() below repeats this; the loads need the new slots now)
-            sc = sn;
-            load_ops();  // after the zx writes: one wave's LDS operations complete in order
-            sp = sp0;
-            sc = sc0;
-          }
-          const bool bad = lane < D && (!finite_(xn) || fabs((double)xn) > a.guard);
-          if (__ballot(bad)) break;
-          if (lane < D) sm.xo[sc][i] = xn;
-          wg_release();
-          if (lane == 0) {
-            lds_st(&sm.out_ready, n);
-            lds_st(&sm.f_pos, n);
-          }
-          last = n;
-          if (!more) break;
+        T bvA[BW], bvB[BW], zv[BW], phA = T(0), phB = T(0), xA = sm.sx[sc][i], xB = T(0);
+        int fr = 0, fs = 0, fw = 0;  // flags of the step after the current one
+        put(-h, xA - h);
+        cbar();
+        lds_st(&sm.f_pos, n);
+        if (n < e) {
           advance();
-          if (!next_ready) {
-            if (!await(p)) {
-              stop = true;
-              break;
-            }
-            load_ops();
+          if (!await(p)) {
+            stop = true;
+          } else {
+            cbar();
+#pragma unroll
+            for (int k = 0; k < BW; k++) zv[k] = sm.zx[i + k];
+            const T* band = sm.sband[sp];
+#pragma unroll
+            for (int k = 0; k < BW; k++) bvA[k] = band[k * D + i];
+            phA = sm.sphi[sp][i];
+            xA = sm.sx[sc][i];
+            cbar();
+            const int sn = sc + 1 == R ? 0 : sc + 1;
+            fr = lds_ld(&sm.ready[sc]);
+            fs = lds_ld(&sm.staged[sn]);
+            fw = lds_ld(&sm.written);
           }
-        }
-        if (!stop && last == p - 1) {  // the first updated state is unusable
-          if (lane == 0) pipe_finish(c, ST_NONFINITE, u - 1);
-          stop = true;
-        }
-        if (stop) {
-          if (lane == 0) lds_st(&sm.abort_, 1);
-        } else if (lane == 0) {
-          wg_release();
-          lds_st(&sm.fold_end, last);
+          // step n with operands (bA, pA, xA); step n+1's go to (bB, pB, xB)
+          auto step = [&](T (&bA)[BW], T& pA, T& xA_, T (&bB)[BW], T& pB, T& xB_)
+              __attribute__((always_inline)) -> int {
+            const int sn = sc + 1 == R ? 0 : sc + 1;
+            const bool more = n < e;
+            if (more) {
+              if (!((fr == n) & (fs == n + 1) & (n + 1 - R < p || fw >= n + 1 - R))) {
+                // not ready when read: wait on fresh flags
+                advance();
+                const bool ok = await(p);
+                n--;
+                sc = sp;
+                sp = sp == 0 ? R - 1 : sp - 1;
+                if (!ok) return 2;
+              }
+              cbar();
+              const T* band = sm.sband[sc];
+#pragma unroll
+              for (int k = 0; k < BW; k++) bB[k] = band[k * D + i];
+              pB = sm.sphi[sc][i];
+              xB_ = sm.sx[sn][i];
+              cbar();
+              const int sn2 = sn + 1 == R ? 0 : sn + 1;
+              fr = lds_ld(&sm.ready[sn]);
+              fs = lds_ld(&sm.staged[sn2]);
+              fw = lds_ld(&sm.written);
+            }
+            const T dxn = band_row13<T>(pA - xA_, bA, zv);
+            put(dxn, xA_ + dxn);
+            if (more) {
+#pragma unroll
+              for (int k = 0; k < BW; k++) zv[k] = sm.zx[i + k];
+            }
+            cbar();
+            lds_st(&sm.f_pos, n);
+            if (!more) return 1;
+            advance();
+            return 0;
+          };
+          while (!stop) {
+            int r = step(bvA, phA, xA, bvB, phB, xB);
+            if (r) break;
+            r = step(bvB, phB, xB, bvA, phA, xA);
+            if (r) break;
+          }
         }
       }
       __builtin_amdgcn_s_setprio(0);
@@ -539,17 +602,23 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
         }
         if (!go) break;
         wg_acquire();
+        // the lane index, opaque to the optimiser here: the per-lane
+        // indices below are recomputed for each element instead of being
+        // hoisted out of the update loop, where they would hold registers
+        // through every role's code
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
         T x[1], phi[1];
-        x[0] = lane < D ? sm.sx[m % R][lane] : T(0);
-        wave_rk4<T, S>(sm.P, dt, x, phi, st, lane);
-        if (lane < D) {
-          sm.sphi[m % R][lane] = phi[0];
+        x[0] = ln < D ? sm.sx[m % R][ln] : T(0);
+        wave_rk4<T, S>(sm.P, dt, x, phi, st, ln);
+        if (ln < D) {
+          sm.sphi[m % R][ln] = phi[0];
           T col[BW];
-          S::jac_band_column(st, lane, dt, col);
+          S::jac_band_column(st, ln, dt, col);
           T* band = sm.sband[m % R];
 #pragma unroll
           for (int r = 0; r < BW; r++) {
-            int row = lane - S::BOFFT + r;
+            int row = ln - S::BOFFT + r;
             row = row < 0 ? row + D : (row >= D ? row - D : row);
             band[(BW - 1 - r) * D + row] = col[r];
           }
