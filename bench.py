@@ -682,20 +682,27 @@ def main():
         seq_ms = e0.elapsed_time(e1) / reps
         extra["sequential_gpu"] = {"value": B * T / (seq_ms / 1e3), "ms_per_solve": seq_ms,
                                    "speedup_of_newton": value / (B * T / (seq_ms / 1e3))}
-        # FP32 solve (tol at FP32 resolution), error against the FP64 oracle
+        # FP32 solve (tol at FP32 resolution), error against the FP64 oracle.
+        # Its window is picked on its own among 48, 56, 64: near the FP32
+        # rounding floor the update count depends strongly on the window
+        # (at W = 64 one box measured 15901 updates against 4946 at W = 56).
         x32, p32 = x0.float(), prm.float()
-        tr32, it32, rs32, st32 = P.solve(P.LORENZ96, x32, p32, w.dt, T, tol=2e-5,
-                                         window=args.window)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(max(1, args.steps // 2)):
-            tr32, it32, rs32, st32 = P.solve(P.LORENZ96, x32, p32, w.dt, T, tol=2e-5,
-                                             window=args.window)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms32 = e0.elapsed_time(e1) / max(1, args.steps // 2)
+        trials32 = {}
+        best = None
+        for w32 in (48, 56, 64):
+            P.solve(P.LORENZ96, x32, p32, w.dt, T, tol=2e-5, window=w32)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            o32 = P.solve(P.LORENZ96, x32, p32, w.dt, T, tol=2e-5, window=w32)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            trials32[str(w32)] = {"ms": round(ms, 2), "updates": int(o32[1][0]), "status": int(o32[3][0])}
+            if int(o32[3][0]) == 0 and (best is None or ms < best[0]):
+                best = (ms, w32, o32)
+        ms32, w32, (tr32, it32, rs32, st32) = best
         fp32 = {"value": B * T / (ms32 / 1e3), "ms_per_solve": ms32, "status": int(st32[0]),
-                "updates": int(it32[0]), "tol": 2e-5}
+                "updates": int(it32[0]), "tol": 2e-5, "window": w32, "window_trials": trials32}
         head_fp32 = tr32[0].double().cpu().numpy()
         extra["fp32"] = fp32
         # the solver that applies one update at a time (the pipelined one
