@@ -127,6 +127,16 @@ def leg_scan_small(P, torch, dev, stream, reps=5):
     orthogonal, so the scan stays bounded)."""
     import workloads as W
     out = {}
+    # the copy bandwidth this box reaches: a 1 GiB device-to-device copy
+    # (read 1 GiB, write 1 GiB), the practical ceiling for a streaming kernel
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    ms_copy = _time(lambda: dst.copy_(src), reps, stream)
+    copy_bw = 2 * src.numel() * 8 / (ms_copy / 1e3)
+    out["copy"] = {"ms": ms_copy, "GB/s": copy_bw / 1e9, "frac_hbm": copy_bw / PEAK_HBM,
+                   "bytes": 2 * src.numel() * 8}
+    del src, dst
+    torch.cuda.empty_cache()
     N = 1 << 24
     for d in (2, 3, 4, 8):
         A = torch.empty((1, N, d, d), dtype=torch.float64, device=dev)
@@ -144,7 +154,7 @@ def leg_scan_small(P, torch, dev, stream, reps=5):
         ms = _time(lambda: P.pint_affine_scan(d, 1, N, P.F64, A, b, None, z, 0, ws, stream), reps, stream)
         byt = N * ((d * d + d) * 8 + d * 8)
         out[f"d{d}"] = {"ms": ms, "GB/s": byt / (ms / 1e3) / 1e9, "frac_hbm": byt / (ms / 1e3) / PEAK_HBM,
-                        "bytes_per_launch": byt, "elements": N}
+                        "frac_of_copy": byt / (ms / 1e3) / copy_bw, "bytes_per_launch": byt, "elements": N}
         del A, b, z, ws
         torch.cuda.empty_cache()
     return out
