@@ -412,9 +412,16 @@ def leg_adjoint(P, torch, dev, stream, B=256, T=16384, window=0, seg=2048, reps=
         res["g"] = P.adjoint(P.LORENZ96, x0, prm, w.dt, traj, g, seg=seg)
 
     ms = _time(back, reps, stream)
+    # algorithmic HBM bytes of the backward pass: the trajectory and the loss
+    # gradient g are each read once (the transposed bands are built inside
+    # the reverse recursion, nothing else is stored)
+    bwd_bytes = 2.0 * B * T * w.d * 8
     return {"instances": B, "T": T, "forward_window": window, "forward_window_tuning": tuning,
             "forward_ms": fwd_ms, "forward_all_ok": bool((status == 0).all()),
             "backward_ms": ms, "grads_per_s": B / (ms / 1e3), "segment": seg,
+            "backward_hbm": {"algorithmic_bytes": bwd_bytes, "GB/s": bwd_bytes / (ms / 1e3) / 1e9,
+                             "frac_hbm": bwd_bytes / (ms / 1e3) / PEAK_HBM,
+                             "per_unit": "2 d 8 bytes per step per instance (trajectory and g)"},
             "fwd_plus_bwd_grads_per_s": B / ((ms + fwd_ms) / 1e3)}
 
 
@@ -444,8 +451,15 @@ def leg_kuramoto(P, torch, dev, stream, window=256, reps=2):
 
     ms32 = _time(run32, reps, stream)
     tr32, it32, rs32, st32 = res["o32"]
+    # algorithmic HBM bytes of the windowed solve, as for the van der Pol
+    # batch: every update reads its window's states and writes them back
+    win_steps = float(iters.double().sum()) * min(window, T)
+    hbm_bytes = win_steps * 2 * w.d * 8
     out = {"instances": w.B, "T": T, "window": window, "ms": ms, "value": w.B * T / (ms / 1e3),
            "all_ok": bool((status == 0).all()), "updates_max": int(iters.max()),
+           "hbm": {"algorithmic_bytes": hbm_bytes, "GB/s": hbm_bytes / (ms / 1e3) / 1e9,
+                   "frac_hbm": hbm_bytes / (ms / 1e3) / PEAK_HBM,
+                   "per_unit": "2 d 8 bytes per window step per update (latency bound: the in-order fold)"},
            "sequential_ms": ms_seq, "speedup_of_newton": ms_seq / ms,
            "fp32": {"ms": ms32, "value": w.B * T / (ms32 / 1e3), "tol": tol32,
                     "all_ok": bool((st32 == 0).all()), "updates_max": int(it32.max())}}
