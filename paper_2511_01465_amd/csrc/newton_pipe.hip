@@ -653,11 +653,469 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
   }
 }
 
+// ---------------------------------------------------- matrix-free systems --
+//
+// The same pipeline for a system whose step Jacobian is applied through the
+// RK4 tangent from the step's stage record instead of being stored (Kuramoto:
+// J_f is a diagonal plus two rank-one terms).  The element of a staged state
+// is Phi and the stage record (the cosines, sines and their sums at the four
+// stage points); the fold applies J_{n-1} to dx_{n-1} through the four stages
+// with the arithmetic of the one-at-a-time solver's fold, so the updates are
+// the same bit for bit.  D = 64 RC components, RC per lane; the ring holds
+// fewer steps than the banded one (a record is 8 D + 8 values).
+constexpr int PIPE_MF_R = 10;  // ring slots (steps)
+
+template <typename T, class S>
+struct PipeSmemMF {
+  static constexpr int D = S::D, R = PIPE_MF_R;
+  T sx[R][D];                       // staged states x_m of iterate u-1
+  T sphi[R][D];                     // Phi(x_m)
+  typename S::Stage srec[R];        // stage record of the step from x_m
+  T xo[R][D];                       // updated states of iterate u (fold -> writer)
+  T P[S::NP], x0[D];
+  double red[PIPE_NT / PINT_WAVE];
+  int staged[R], ready[R];
+  int f_pos, written, pprev, p_u, e_u, fold_end, abort_;  // as in PipeSmem
+};
+
+template <typename T, class S>
+__global__ __launch_bounds__(PIPE_NT) void k_newton_pipe_mf(PipeKArgs a, int G) {
+  constexpr int D = S::D, RC = S::R, R = PIPE_MF_R;
+  static_assert(S::MATFREE && D == PINT_WAVE * RC, "whole lanes, RC components each");
+  extern __shared__ __align__(16) unsigned char dyn[];
+  PipeSmemMF<T, S>& sm = *reinterpret_cast<PipeSmemMF<T, S>*>(dyn);
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  const int64_t inst = blockIdx.x / G;
+  const int g = blockIdx.x % G;
+  const int64_t Tn = a.T, W = a.window;
+  const T dt = (T)a.dt;
+  PipeCtl* c = a.ctl + inst;
+  PipeRec* rec = a.rec + inst * G;
+  T* X = static_cast<T*>(a.traj) + inst * Tn * D;
+  const uint64_t lim = a.wait_limit;
+  uint32_t gen = 0;
+
+  for (int i = tid; i < S::NP; i += PIPE_NT)
+    sm.P[i] = static_cast<const T*>(a.params)[inst * a.pstride + i];
+  for (int i = tid; i < D; i += PIPE_NT) sm.x0[i] = static_cast<const T*>(a.x0)[inst * D + i];
+  __syncthreads();
+  if (a.guess == 0)
+    for (int64_t idx = (int64_t)g * PIPE_NT + tid; idx < Tn * D; idx += (int64_t)G * PIPE_NT)
+      X[idx] = sm.x0[idx % D];
+  if (g == 0 && tid == 0 && Tn == 0) pipe_finish(c, ST_OK, 0);
+  pipe_barrier(c, G, gen, lim);  // the initial iterate is in memory
+
+  auto spin = [&](uint64_t& it) -> bool {
+    if (++it >= lim) {
+      atomicOr(&c->err, 1u);
+      lds_st(&sm.abort_, 1);
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return lds_ld(&sm.abort_) != 0;
+  };
+
+  for (int64_t u = g + 1;; u += G) {
+    if (tid == 0) {
+      for (int r = 0; r < R; r++) {
+        sm.staged[r] = -1;
+        sm.ready[r] = -1;
+      }
+      sm.f_pos = -1;
+      sm.written = -1;
+      sm.pprev = 0;
+      sm.p_u = 0;
+      sm.e_u = 0;
+      sm.fold_end = -1;
+      sm.abort_ = pipe_stop(c, u) ? 1 : 0;
+    }
+    __syncthreads();
+    if (sm.abort_) break;
+    const int64_t aprev = (u - 2) % G;  // agent of update u-1 (u >= 2)
+
+    if (wv == 1) {
+      // ------------------------------------------------------- loader ---
+      __builtin_amdgcn_s_setprio(2);
+      uint64_t it = 0;
+      int64_t pprev = 1, eprev = 0;  // update 0: none; iterate 0 is final everywhere
+      if (u >= 2) {
+        for (;;) {
+          const unsigned long long s = gld(&rec[aprev].start);
+          if ((int64_t)(s >> 32) == u - 1) {
+            pprev = (int64_t)(s & 0xffffffffull);
+            break;
+          }
+          if (pipe_stop(c, u)) {
+            lds_st(&sm.abort_, 1);
+            break;
+          }
+          if (spin(it)) break;
+        }
+        eprev = (W >= Tn - pprev + 1) ? Tn : pprev + W - 1;
+      }
+      if (lane == 0) {
+        lds_st(&sm.f_pos, (int)(pprev - 1));
+        wg_release();
+        lds_st(&sm.pprev, (int)pprev);
+      }
+      int64_t final_upto = u >= 2 ? pprev - 1 : Tn;
+      int64_t m = pprev - 1;
+      auto take_prog = [&](unsigned long long pr) {
+        const int64_t tag = (int64_t)(pr >> 32);
+        if (tag > u - 1) final_upto = Tn;
+        else if (tag == u - 1 && (int64_t)(pr & 0xffffffffull) > final_upto) final_upto = (int64_t)(pr & 0xffffffffull);
+      };
+      uint32_t polls = 0;
+      while (!lds_ld(&sm.abort_) && lds_ld(&sm.fold_end) < 0 && m <= Tn) {
+        const int e_u = lds_ld(&sm.e_u);
+        int64_t lim_m = (int64_t)lds_ld(&sm.f_pos) + R - 1;  // ring space
+        if (e_u > 0 && lim_m > e_u) lim_m = e_u;
+        if (lim_m > Tn) lim_m = Tn;
+        if (m > lim_m) {
+          if (spin(it)) break;
+          continue;
+        }
+        if (m > final_upto && m <= eprev) {
+          take_prog(gld(&rec[aprev].prog));
+          if (m > final_upto) {
+            if ((++polls & 31) == 0 && pipe_stop(c, u)) {
+              lds_st(&sm.abort_, 1);
+              break;
+            }
+            if (spin(it)) break;
+            continue;
+          }
+        }
+        int64_t hi = lim_m;
+        if (hi > m + 3) hi = m + 3;
+        if (m <= eprev && final_upto < eprev && hi > final_upto) hi = final_upto;
+        T v[4][RC];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int64_t mm = m + j;
+#pragma unroll
+          for (int r = 0; r < RC; r++) {
+            v[j][r] = T(0);
+            if (mm <= hi) v[j][r] = mm == 0 ? sm.x0[lane + PINT_WAVE * r] : pld(X + (mm - 1) * D + lane + PINT_WAVE * r);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int64_t mm = m + j;
+#pragma unroll
+          for (int r = 0; r < RC; r++)
+            if (mm <= hi) sm.sx[mm % R][lane + PINT_WAVE * r] = v[j][r];
+        }
+        wg_release();
+        if (lane == 0)
+          for (int64_t mm = m; mm <= hi; mm++) lds_st(&sm.staged[mm % R], (int)mm);
+        m = hi + 1;
+        it = 0;
+      }
+      __builtin_amdgcn_s_setprio(0);
+    } else if (wv == 2) {
+      // ------------------------------------------------------- writer ---
+      // As in the banded pipeline: the window start, then the updated states
+      // in order, each checked against the guard; the first that fails is
+      // the cut.
+      __builtin_amdgcn_s_setprio(2);
+      uint64_t it = 0;
+      int p = 0;
+      while (!lds_ld(&sm.abort_) && (p = lds_ld(&sm.p_u)) == 0)
+        if (spin(it)) break;
+      if (p > 0 && !lds_ld(&sm.abort_)) {
+        wg_acquire();
+        const int e = lds_ld(&sm.e_u);
+        if (lane == 0) {
+          gst(&rec[g].start, ((unsigned long long)u << 32) | (unsigned)p);
+          wait_stores();
+          gst(&rec[g].prog, ((unsigned long long)u << 32) | (unsigned)(p - 1));
+        }
+        int w = p - 1, fe = -1;
+        it = 0;
+        for (;;) {
+          const int avail = lds_ld(&sm.f_pos);
+          if (avail > w) {
+            wg_acquire();
+            const int hi = avail - w > 4 ? w + 4 : avail;
+            T v[4][RC];
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+#pragma unroll
+              for (int r = 0; r < RC; r++)
+                if (w + 1 + j <= hi) v[j][r] = sm.xo[(w + 1 + j) % R][lane + PINT_WAVE * r];
+            int n = w + 1;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              if (n > hi) break;
+              bool badj = false;
+#pragma unroll
+              for (int r = 0; r < RC; r++) badj = badj || !finite_(v[j][r]) || fabs((double)v[j][r]) > a.guard;
+              if (__ballot(badj)) break;
+#pragma unroll
+              for (int r = 0; r < RC; r++) pst(X + (int64_t)(n - 1) * D + lane + PINT_WAVE * r, v[j][r]);
+              n++;
+            }
+            const int last = n - 1;
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            if (lane == 0) lds_st(&sm.written, last);
+            wait_stores();
+            if (lane == 0 && last > w) gst(&rec[g].prog, ((unsigned long long)u << 32) | (unsigned)last);
+            w = last;
+            it = 0;
+            if (n <= hi) {
+              fe = n - 1;
+              break;
+            }
+            if (w >= e) {
+              fe = e;
+              break;
+            }
+            continue;
+          }
+          if (lds_ld(&sm.abort_)) break;
+          if (spin(it)) break;
+        }
+        if (fe >= 0 && !lds_ld(&sm.abort_)) {
+          if (fe == p - 1) {
+            if (lane == 0) {
+              pipe_finish(c, ST_NONFINITE, u - 1);
+              lds_st(&sm.abort_, 1);
+            }
+          } else {
+            if (lane == 0) {
+              wg_release();
+              lds_st(&sm.fold_end, fe);
+            }
+            if (fe < e && u >= 2) {
+              it = 0;
+              for (;;) {
+                const unsigned long long pr = gld(&rec[aprev].prog);
+                const int64_t tag = (int64_t)(pr >> 32);
+                if (tag > u - 1 || (tag == u - 1 && (int64_t)(pr & 0xffffffffull) >= e)) break;
+                const unsigned long long s0 = gld(&rec[aprev].start);
+                const int64_t pp = (int64_t)(s0 & 0xffffffffull);
+                if ((int64_t)(s0 >> 32) == u - 1 && ((W >= Tn - pp + 1) ? Tn : pp + W - 1) < fe + 1) break;
+                if (pipe_stop(c, u)) {
+                  lds_st(&sm.abort_, 1);
+                  break;
+                }
+                if (spin(it)) break;
+              }
+            }
+            if (lane == 0 && !lds_ld(&sm.abort_))
+              gst(&rec[g].prog, ((unsigned long long)u << 32) | (unsigned long long)Tn);
+          }
+        }
+      }
+      __builtin_amdgcn_s_setprio(0);
+    } else if (wv == 0) {
+      // --------------------------------------------------------- fold ---
+      __builtin_amdgcn_s_setprio(3);
+      uint64_t it = 0;
+      int pprev = 0;
+      while ((pprev = lds_ld(&sm.pprev)) == 0)
+        if (spin(it)) break;
+      const int tn = (int)Tn;
+      bool stop = lds_ld(&sm.abort_) != 0 || pprev == 0;
+      int n = pprev;
+      int sp = (n - 1) % R, sc = n % R;
+      auto advance = [&]() {
+        n++;
+        sp = sc;
+        sc = sc + 1 == R ? 0 : sc + 1;
+      };
+      // element n-1 and state n (and in the fold the output slot's previous
+      // occupant taken by the writer), as in the banded pipeline
+      auto await = [&](int xo_from) -> bool {
+        uint64_t w = 0;
+        for (;;) {
+          const int fr = lds_ld(&sm.ready[sp]), fs = lds_ld(&sm.staged[sc]), fw = lds_ld(&sm.written);
+          if ((fr == n - 1) & (fs == n) & (xo_from == 0 || n - R < xo_from || fw >= n - R)) break;
+          if (xo_from != 0 && lds_ld(&sm.fold_end) >= 0) return false;
+          if (spin(w)) return false;
+        }
+        wg_acquire();
+        return true;
+      };
+      T h[RC];
+      bool violated = false, nonfinite = false;
+      while (!stop) {  // the first violation of iterate u-1 at or after p_{u-1}
+        if (n > tn) {
+          if (lane == 0) pipe_finish(c, ST_OK, u - 1);
+          stop = true;
+          break;
+        }
+        if (!await(0)) {
+          stop = true;
+          break;
+        }
+        bool viol = false, nf = false;
+#pragma unroll
+        for (int r = 0; r < RC; r++) {
+          h[r] = sm.sx[sc][lane + PINT_WAVE * r] - sm.sphi[sp][lane + PINT_WAVE * r];
+          viol = viol || !(fabs((double)h[r]) < a.tol);
+          nf = nf || !finite_(h[r]);
+        }
+        violated = __ballot(viol) != 0;
+        nonfinite = __ballot(nf) != 0;
+        if (violated) break;
+        if (lane == 0) lds_st(&sm.f_pos, n);
+        advance();
+      }
+      if (!stop) {
+        if (nonfinite) {
+          if (lane == 0) pipe_finish(c, ST_NONFINITE, u - 1);
+          stop = true;
+        } else if (u - 1 >= a.max_iter) {
+          if (lane == 0) pipe_finish(c, ST_NOT_CONVERGED, u - 1);
+          stop = true;
+        }
+      }
+      if (stop) {
+        if (lane == 0) lds_st(&sm.abort_, 1);
+      } else {
+        const int p = n;
+        const int e = (W >= Tn - p + 1) ? tn : (int)(p + W - 1);
+        if (lane == 0) {
+          lds_st(&sm.e_u, e);
+          wg_release();
+          lds_st(&sm.p_u, p);
+        }
+        const T h2 = T(0.5) * dt, c6 = dt / T(6), Kc = sm.P[0];
+        T v[RC];  // dx_n, this lane's components
+        // dx_p = -h_p
+#pragma unroll
+        for (int r = 0; r < RC; r++) {
+          v[r] = -h[r];
+          sm.xo[sc][lane + PINT_WAVE * r] = sm.sx[sc][lane + PINT_WAVE * r] + v[r];
+        }
+        asm volatile("" ::: "memory");
+        lds_st(&sm.f_pos, n);
+        while (n < e) {
+          advance();
+          {
+            const int fr = lds_ld(&sm.ready[sp]), fs = lds_ld(&sm.staged[sc]), fw = lds_ld(&sm.written);
+            if (!((fr == n - 1) & (fs == n) & (n - R < p || fw >= n - R))) {
+              if (!await(p)) break;
+            } else {
+              wg_acquire();
+            }
+          }
+          // dx_n = J(x_{n-1}) dx_{n-1} + (Phi(x_{n-1}) - x_n), J through the
+          // RK4 tangent from step n-1's stage record
+          const typename S::Stage* st = &sm.srec[sp];
+          T z[RC], uu[RC], acc[RC];
+#pragma unroll
+          for (int r = 0; r < RC; r++) {
+            z[r] = sm.sphi[sp][lane + PINT_WAVE * r] - sm.sx[sc][lane + PINT_WAVE * r];
+            uu[r] = v[r];
+          }
+#pragma unroll
+          for (int s = 0; s < 4; s++) {
+            T cs[RC], sn[RC];
+            T pa = T(0), pb = T(0);
+#pragma unroll
+            for (int r = 0; r < RC; r++) {
+              cs[r] = st->c[s][lane + PINT_WAVE * r];
+              sn[r] = st->s[s][lane + PINT_WAVE * r];
+              pa += cs[r] * uu[r];
+              pb += sn[r] * uu[r];
+            }
+            const T C = st->C[s], Sg = st->S[s];
+            wave_sum2_dpp(pa, pb);
+            const T w = (s == 0 || s == 3) ? T(1) : T(2);
+            const T cc = (s == 2) ? dt : h2;
+#pragma unroll
+            for (int r = 0; r < RC; r++) {
+              const T K = Kc * (cs[r] * pa + sn[r] * pb) - Kc * (cs[r] * C + sn[r] * Sg) * uu[r];
+              acc[r] = (s == 0) ? K : acc[r] + w * K;
+              uu[r] = v[r] + cc * K;
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < RC; r++) {
+            z[r] = (v[r] + c6 * acc[r]) + z[r];
+            v[r] = z[r];
+            sm.xo[sc][lane + PINT_WAVE * r] = sm.sx[sc][lane + PINT_WAVE * r] + z[r];
+          }
+          asm volatile("" ::: "memory");
+          lds_st(&sm.f_pos, n);
+        }
+      }
+      __builtin_amdgcn_s_setprio(0);
+    } else if (pipe_elem_index(wv) >= 0) {
+      // ----------------------------------------------------- elements ---
+      const int e = pipe_elem_index(wv);
+      uint64_t it = 0;
+      int pprev = 0;
+      while ((pprev = lds_ld(&sm.pprev)) == 0)
+        if (spin(it)) break;
+      for (int64_t m = pprev - 1 + e; pprev > 0 && m < Tn; m += PIPE_NE) {
+        bool go = false;
+        it = 0;
+        for (;;) {
+          if (lds_ld(&sm.abort_) || lds_ld(&sm.fold_end) >= 0) break;
+          const int eu = lds_ld(&sm.e_u);
+          if (eu > 0 && m > eu - 1) break;
+          if (lds_ld(&sm.staged[m % R]) == (int)m) {
+            go = true;
+            break;
+          }
+          if (spin(it)) break;
+        }
+        if (!go) break;
+        wg_acquire();
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        T x[RC], phi[RC];
+#pragma unroll
+        for (int r = 0; r < RC; r++) x[r] = sm.sx[m % R][ln + PINT_WAVE * r];
+        wave_rk4<T, S>(sm.P, dt, x, phi, &sm.srec[m % R], ln);
+#pragma unroll
+        for (int r = 0; r < RC; r++) sm.sphi[m % R][ln + PINT_WAVE * r] = phi[r];
+        wg_release();
+        if (lane == 0) lds_st(&sm.ready[m % R], (int)m);
+      }
+    }
+    __syncthreads();  // every role of update u has finished
+    if (sm.abort_) break;
+  }
+
+  // the iteration has ended: every agent stops; final residual over all steps
+  pipe_barrier(c, G, gen, lim);
+  double r = 0.0;
+  for (int64_t nn = 1 + (int64_t)g * (PIPE_NT / PINT_WAVE) + wv; nn <= Tn; nn += (int64_t)G * (PIPE_NT / PINT_WAVE)) {
+    T xp[RC], xc[RC], phi[RC];
+#pragma unroll
+    for (int q = 0; q < RC; q++) {
+      const int i = lane + PINT_WAVE * q;
+      xp[q] = nn == 1 ? sm.x0[i] : pld(X + (nn - 2) * D + i);
+      xc[q] = pld(X + (nn - 1) * D + i);
+    }
+    wave_rk4<T, S>(sm.P, dt, xp, phi, nullptr, lane);
+#pragma unroll
+    for (int q = 0; q < RC; q++) r = acc_norm(r, xc[q] - phi[q]);
+  }
+  r = wave_max(r);
+  if (lane == 0) atomic_max_nonneg(reinterpret_cast<double*>(&c->rmax), r);
+  pipe_barrier(c, G, gen, lim);
+  if (g == 0 && tid == 0) {
+    const unsigned long long d = gld(&c->done);
+    const bool err = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    a.iters[inst] = d ? done_iters(d) : 0;
+    a.resid[inst] = __longlong_as_double((long long)gld(&c->rmax));
+    a.status[inst] = (err || d == 0) ? ST_DEVICE : done_status(d);
+  }
+}
+
 // ------------------------------------------------------------ host side --
 
 template <typename T, typename F>
 static int dispatch_pipe_sys(int system, int d, F&& f) {
   if (system == 5 && d == 40) return f(DSysL96<T, 40>{});
+  if (system == 6 && d == 128) return f(DSysKur<T, 128>{});
+  if (system == 6 && d == 64) return f(DSysKur<T, 64>{});
   return ST_UNSUPPORTED;
 }
 
@@ -680,7 +1138,21 @@ static int pipe_agents(const SolveArgs& a) {
 }
 
 template <typename T, class S>
-static size_t pipe_lds() { return sizeof(PipeSmem<T, S>); }
+static size_t pipe_lds() {
+  if constexpr (S::MATFREE)
+    return sizeof(PipeSmemMF<T, S>);
+  else
+    return sizeof(PipeSmem<T, S>);
+}
+
+// The kernel of a system: banded (Lorenz-96) or matrix-free (Kuramoto).
+template <typename T, class S>
+static const void* pipe_kernel() {
+  if constexpr (S::MATFREE)
+    return reinterpret_cast<const void*>(&k_newton_pipe_mf<T, S>);
+  else
+    return reinterpret_cast<const void*>(&k_newton_pipe<T, S>);
+}
 
 size_t pipe_ws_bytes(const SolveArgs& a) {
   const int G = pipe_agents(a);
@@ -689,8 +1161,9 @@ size_t pipe_ws_bytes(const SolveArgs& a) {
   return align_up((size_t)a.B * sizeof(PipeCtl)) + align_up((size_t)a.B * G * sizeof(PipeRec));
 }
 
-// Runs the pipelined solve when it applies (Lorenz-96, windowed, a batch
-// small enough for one agent per compute unit); *used says whether it ran.
+// Runs the pipelined solve when it applies (Lorenz-96 or Kuramoto, windowed,
+// a batch small enough for one agent per compute unit); *used says whether
+// it ran.
 int pipe_solve(const SolveArgs& a, bool* used) {
   *used = false;
   const int G = pipe_agents(a);
@@ -704,13 +1177,13 @@ int pipe_solve(const SolveArgs& a, bool* used) {
     const size_t lds = pipe_lds<T, S>();
     static bool attr_set = false;
     if (!attr_set) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_newton_pipe<T, S>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      if (hipFuncSetAttribute(pipe_kernel<T, S>(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+          hipSuccess)
         return ST_DEVICE;
       attr_set = true;
     }
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_newton_pipe<T, S>, PIPE_NT, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pipe_kernel<T, S>(), PIPE_NT, lds) != hipSuccess ||
         per_cu < 1)
       return ST_OK;  // not resident: the caller uses another solver
     char* w = static_cast<char*>(a.ws);
@@ -736,7 +1209,7 @@ int pipe_solve(const SolveArgs& a, bool* used) {
     k.wait_limit = wait_limit();
     int Gv = G;
     void* args[] = {&k, &Gv};
-    const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_newton_pipe<T, S>),
+    const hipError_t e = hipLaunchCooperativeKernel(pipe_kernel<T, S>(),
                                                     dim3((unsigned)(a.B * G)), dim3(PIPE_NT), args, lds,
                                                     a.stream);
     if (e != hipSuccess) {

@@ -1,6 +1,6 @@
-"""The pipelined windowed solver for Lorenz-96 (consecutive Newton updates
-overlapping on separate workgroups) against the solver that applies one
-update at a time, and against the oracle.  Both GPU solvers compute each
+"""The pipelined windowed solvers for Lorenz-96 and Kuramoto (consecutive
+Newton updates overlapping on separate workgroups) against the solver that
+applies one update at a time, and against the oracle.  Both GPU solvers compute each
 element and each fold step with the same arithmetic in the same order, so
 the bar between them is bit for bit: same iteration count, same status,
 identical trajectories.  Against the oracle: the same iterate to 1e-10 on
@@ -19,13 +19,14 @@ def _t(a, dtype=torch.float64):
     return torch.tensor(np.asarray(a), dtype=dtype, device=DEV)
 
 
-def _both(pint, w, T, dtype=torch.float64, **kw):
+def _both(pint, w, T, dtype=torch.float64, system=None, **kw):
     """The same solve with the pipelined solver and with the other one."""
     out = {}
+    system = pint.LORENZ96 if system is None else system
     try:
         for pipe in (True, False):
             pint.pint_set_dense_pipeline(pipe)
-            out[pipe] = pint.solve(pint.LORENZ96, _t(w.x0, dtype), _t(w.params, dtype), w.dt, T, **kw)
+            out[pipe] = pint.solve(system, _t(w.x0, dtype), _t(w.params, dtype), w.dt, T, **kw)
             torch.cuda.synchronize()
     finally:
         pint.pint_set_dense_pipeline(True)
@@ -99,3 +100,69 @@ def test_pipeline_end_conditions(pint, orc):
     torch.cuda.synchronize()
     ref = orc.newton(w.system, w.params[0], w.dt, 10, w.x0[0], tol=1e-10, window=24, max_iter=100)
     assert int(status[0]) == 0 and int(iters[0]) == ref["iters"]
+
+
+# ----------------------------------------------------------------- Kuramoto --
+# The matrix-free pipeline: each agent's elements are Phi and the stage record,
+# its fold applies J through the RK4 tangent; the same bar against the
+# one-at-a-time solver (bit for bit) and the oracle (same iterate).
+
+@pytest.mark.parametrize("T,window,B,d", [(64, 16, 2, 128), (256, 64, 2, 128), (200, 300, 3, 128),
+                                          (512, 64, 8, 128), (333, 29, 4, 128), (300, 40, 2, 64)])
+def test_kuramoto_pipeline_equals_one_at_a_time(pint, T, window, B, d):
+    w = W.kuramoto(B=B, d=d, T=T)
+    print(f"[pipe kuramoto] T={T} W={window} B={B} d={d}", flush=True)
+    (tp, ip, rp, sp), (to, io, ro, so) = _both(pint, w, T, system=pint.KURAMOTO, tol=1e-10, window=window)
+    assert torch.equal(sp, so) and bool((sp == 0).all())
+    assert torch.equal(ip, io)
+    assert torch.equal(tp, to)
+    assert torch.equal(rp, ro)
+
+
+def test_kuramoto_pipeline_fp32_equals_one_at_a_time(pint):
+    w = W.kuramoto(B=2, T=600)
+    (tp, ip, rp, sp), (to, io, ro, so) = _both(pint, w, 600, dtype=torch.float32, system=pint.KURAMOTO,
+                                               tol=5e-5, window=64)
+    assert torch.equal(sp, so) and torch.equal(ip, io) and torch.equal(tp, to)
+
+
+@pytest.mark.parametrize("T,window", [(256, 64), (150, 11)])
+def test_kuramoto_pipeline_same_iterate_as_oracle(pint, orc, T, window):
+    w = W.kuramoto(B=1, T=T)
+    ref = orc.newton(w.system, w.params[0], w.dt, T, w.x0[0], tol=1e-10, window=window,
+                     max_iter=4 * T)
+    traj, iters, resid, status = pint.solve(pint.KURAMOTO, _t(w.x0), _t(w.params), w.dt, T,
+                                            tol=1e-10, window=window, max_iter=4 * T)
+    torch.cuda.synchronize()
+    assert int(status[0]) == ref["status"] == 0 and int(iters[0]) == ref["iters"]
+    assert np.abs(traj[0].cpu().numpy() - ref["traj"]).max() <= 1e-10
+
+
+def test_kuramoto_pipeline_end_conditions(pint, orc):
+    """The update limit (the oracle's iterate after max_iter updates), a guard
+    that cuts updates (the phases grow past it), and a non-finite start."""
+    w = W.kuramoto(B=1, T=300)
+    for max_iter in (1, 4):
+        ref = orc.newton(w.system, w.params[0], w.dt, 300, w.x0[0], tol=1e-10, window=32,
+                         max_iter=max_iter)
+        traj, iters, resid, status = pint.solve(pint.KURAMOTO, _t(w.x0), _t(w.params), w.dt, 300,
+                                                tol=1e-10, window=32, max_iter=max_iter)
+        torch.cuda.synchronize()
+        assert int(status[0]) == pint.NOT_CONVERGED == ref["status"]
+        assert int(iters[0]) == max_iter == ref["iters"]
+        assert np.abs(traj[0].cpu().numpy() - ref["traj"]).max() <= 1e-10
+    guard = float(np.abs(w.x0).max()) + 0.5
+    ref = orc.newton(w.system, w.params[0], w.dt, 300, w.x0[0], tol=1e-10, window=64,
+                     guard=guard, max_iter=3000)
+    traj, iters, resid, status = pint.solve(pint.KURAMOTO, _t(w.x0), _t(w.params), w.dt, 300,
+                                            tol=1e-10, window=64, guard=guard, max_iter=3000)
+    torch.cuda.synchronize()
+    assert int(status[0]) == ref["status"] and int(iters[0]) == ref["iters"]
+    if ref["status"] == 0:
+        assert np.abs(traj[0].cpu().numpy() - ref["traj"]).max() <= 1e-10
+    x0 = w.x0.copy()
+    x0[0, 5] = np.nan
+    traj, iters, resid, status = pint.solve(pint.KURAMOTO, _t(x0), _t(w.params), w.dt, 300,
+                                            tol=1e-10, window=32)
+    torch.cuda.synchronize()
+    assert int(status[0]) == pint.NONFINITE and int(iters[0]) == 0
