@@ -664,6 +664,23 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
 // the same bit for bit.  D = 64 RC components, RC per lane; the ring holds
 // fewer steps than the banded one (a record is 8 D + 8 values).
 constexpr int PIPE_MF_R = 10;  // ring slots (steps)
+#ifndef PIPE_MF_NT
+#define PIPE_MF_NT 768
+#endif
+#ifndef PIPE_MF_SKIP0
+#define PIPE_MF_SKIP0 0
+#endif
+constexpr int PIPE_MF_NW = PIPE_MF_NT / PINT_WAVE;
+// element waves: 3, 4, ... (with PIPE_MF_SKIP0, not those on the fold's SIMD, w % 4 == 0)
+__host__ __device__ constexpr int mf_elem_index(int wv) {
+  if (wv < 3) return -1;
+  if (PIPE_MF_SKIP0 && wv % 4 == 0) return -1;
+  int e = 0;
+  for (int w = 3; w < wv; w++)
+    if (!(PIPE_MF_SKIP0 && w % 4 == 0)) e++;
+  return e;
+}
+constexpr int PIPE_MF_NE = mf_elem_index(PIPE_MF_NW - 1) + 1;
 
 template <typename T, class S>
 struct PipeSmemMF {
@@ -673,13 +690,12 @@ struct PipeSmemMF {
   typename S::Stage srec[R];        // stage record of the step from x_m
   T xo[R][D];                       // updated states of iterate u (fold -> writer)
   T P[S::NP], x0[D];
-  double red[PIPE_NT / PINT_WAVE];
   int staged[R], ready[R];
   int f_pos, written, pprev, p_u, e_u, fold_end, abort_;  // as in PipeSmem
 };
 
 template <typename T, class S>
-__global__ __launch_bounds__(PIPE_NT) void k_newton_pipe_mf(PipeKArgs a, int G) {
+__global__ __launch_bounds__(PIPE_MF_NT) void k_newton_pipe_mf(PipeKArgs a, int G) {
   constexpr int D = S::D, RC = S::R, R = PIPE_MF_R;
   static_assert(S::MATFREE && D == PINT_WAVE * RC, "whole lanes, RC components each");
   extern __shared__ __align__(16) unsigned char dyn[];
@@ -695,12 +711,12 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe_mf(PipeKArgs a, int G) 
   const uint64_t lim = a.wait_limit;
   uint32_t gen = 0;
 
-  for (int i = tid; i < S::NP; i += PIPE_NT)
+  for (int i = tid; i < S::NP; i += PIPE_MF_NT)
     sm.P[i] = static_cast<const T*>(a.params)[inst * a.pstride + i];
-  for (int i = tid; i < D; i += PIPE_NT) sm.x0[i] = static_cast<const T*>(a.x0)[inst * D + i];
+  for (int i = tid; i < D; i += PIPE_MF_NT) sm.x0[i] = static_cast<const T*>(a.x0)[inst * D + i];
   __syncthreads();
   if (a.guess == 0)
-    for (int64_t idx = (int64_t)g * PIPE_NT + tid; idx < Tn * D; idx += (int64_t)G * PIPE_NT)
+    for (int64_t idx = (int64_t)g * PIPE_MF_NT + tid; idx < Tn * D; idx += (int64_t)G * PIPE_MF_NT)
       X[idx] = sm.x0[idx % D];
   if (g == 0 && tid == 0 && Tn == 0) pipe_finish(c, ST_OK, 0);
   pipe_barrier(c, G, gen, lim);  // the initial iterate is in memory
@@ -1044,14 +1060,14 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe_mf(PipeKArgs a, int G) 
         }
       }
       __builtin_amdgcn_s_setprio(0);
-    } else if (pipe_elem_index(wv) >= 0) {
+    } else if (mf_elem_index(wv) >= 0) {
       // ----------------------------------------------------- elements ---
-      const int e = pipe_elem_index(wv);
+      const int e = mf_elem_index(wv);
       uint64_t it = 0;
       int pprev = 0;
       while ((pprev = lds_ld(&sm.pprev)) == 0)
         if (spin(it)) break;
-      for (int64_t m = pprev - 1 + e; pprev > 0 && m < Tn; m += PIPE_NE) {
+      for (int64_t m = pprev - 1 + e; pprev > 0 && m < Tn; m += PIPE_MF_NE) {
         bool go = false;
         it = 0;
         for (;;) {
@@ -1085,7 +1101,7 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe_mf(PipeKArgs a, int G) 
   // the iteration has ended: every agent stops; final residual over all steps
   pipe_barrier(c, G, gen, lim);
   double r = 0.0;
-  for (int64_t nn = 1 + (int64_t)g * (PIPE_NT / PINT_WAVE) + wv; nn <= Tn; nn += (int64_t)G * (PIPE_NT / PINT_WAVE)) {
+  for (int64_t nn = 1 + (int64_t)g * (PIPE_MF_NT / PINT_WAVE) + wv; nn <= Tn; nn += (int64_t)G * (PIPE_MF_NT / PINT_WAVE)) {
     T xp[RC], xc[RC], phi[RC];
 #pragma unroll
     for (int q = 0; q < RC; q++) {
@@ -1145,6 +1161,15 @@ static size_t pipe_lds() {
     return sizeof(PipeSmem<T, S>);
 }
 
+// Threads per agent of a system's kernel.
+template <class S>
+static constexpr int pipe_nt() {
+  if constexpr (S::MATFREE)
+    return PIPE_MF_NT;
+  else
+    return PIPE_NT;
+}
+
 // The kernel of a system: banded (Lorenz-96) or matrix-free (Kuramoto).
 template <typename T, class S>
 static const void* pipe_kernel() {
@@ -1183,7 +1208,8 @@ int pipe_solve(const SolveArgs& a, bool* used) {
       attr_set = true;
     }
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pipe_kernel<T, S>(), PIPE_NT, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pipe_kernel<T, S>(), pipe_nt<S>(), lds) !=
+            hipSuccess ||
         per_cu < 1)
       return ST_OK;  // not resident: the caller uses another solver
     char* w = static_cast<char*>(a.ws);
@@ -1210,7 +1236,7 @@ int pipe_solve(const SolveArgs& a, bool* used) {
     int Gv = G;
     void* args[] = {&k, &Gv};
     const hipError_t e = hipLaunchCooperativeKernel(pipe_kernel<T, S>(),
-                                                    dim3((unsigned)(a.B * G)), dim3(PIPE_NT), args, lds,
+                                                    dim3((unsigned)(a.B * G)), dim3(pipe_nt<S>()), args, lds,
                                                     a.stream);
     if (e != hipSuccess) {
       (void)hipGetLastError();

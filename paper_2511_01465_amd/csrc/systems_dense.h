@@ -254,8 +254,10 @@ struct DSysKur {
     T ls = T(0), lc = T(0);
 #pragma unroll
     for (int r = 0; r < R; r++) {
-      sn[r] = sin(x[r]);
-      cs[r] = cos(x[r]);
+      if constexpr (sizeof(T) == 8)
+        sincos(x[r], &sn[r], &cs[r]);  // one argument reduction for both
+      else
+        sincosf(x[r], &sn[r], &cs[r]);
       ls += sn[r];
       lc += cs[r];
     }
