@@ -149,15 +149,18 @@ void pint_set_wait_limit(uint64_t polls);
  * applies: keep sleeps small (a few hundred at most). */
 void pint_set_scan_delay(uint32_t sleeps);
 
-/* The pipelined Lorenz-96 kernels (d = 40), on != 0 by default:
- *  - windowed solves (pint_solve of PINT_SYS_LORENZ96, window >= 1, batches
- *    of up to 1/4 as many instances as compute units): the pipelined
- *    solver, in which consecutive Newton updates overlap in time on separate
- *    workgroups; 0 the solver that applies one update at a time.  Both
- *    compute the same iteration (same windows, same accepted updates).
- *  - pint_adjoint: the fused reverse pass, elements built inside the
- *    recursion; 0 the two-kernel path (elements stored per segment, then
- *    the banded scan).  Same recursion, summation order aside.
+/* The pipelined kernels, on != 0 by default:
+ *  - windowed solves of the dense systems (pint_solve of PINT_SYS_LORENZ96
+ *    with d = 40, or PINT_SYS_KURAMOTO with d = 64 or 128; window >= 1;
+ *    batches of up to 1/4 as many instances as compute units): the
+ *    pipelined solver, in which consecutive Newton updates overlap in time
+ *    on separate workgroups; 0 the solver that applies one update at a
+ *    time.  Both compute the same iteration (same windows, same accepted
+ *    updates, the same states bit for bit).
+ *  - pint_adjoint of Lorenz-96: the fused reverse pass, elements built
+ *    inside the recursion; 0 the two-kernel path (elements stored per
+ *    segment, then the banded scan).  Same recursion, summation order
+ *    aside.
  * Process-wide; applies to launches enqueued (and workspace queries made)
  * after the call. */
 void pint_set_dense_pipeline(int on);
