@@ -18,21 +18,26 @@ def _t(a, dtype=torch.float64):
     return torch.tensor(np.asarray(a), dtype=dtype, device=DEV)
 
 
-def _solve_limited(pint, *args, **kw):
+def _solve_limited(pint, *args, pipe=True, **kw):
+    """A solve whose every cross-workgroup wait gives up at once; pipe picks
+    the pipelined windowed solver (True) or the one-at-a-time one."""
     try:
         pint.pint_set_wait_limit(0)
+        pint.pint_set_dense_pipeline(pipe)
         out = pint.solve(*args, **kw)
         torch.cuda.synchronize()
     finally:
         pint.pint_set_wait_limit(pint.WAIT_LIMIT_DEFAULT)
+        pint.pint_set_dense_pipeline(True)
     return out
 
 
-def test_dense_banded_wait_gives_up(pint, orc):
+@pytest.mark.parametrize("pipe", [True, False])
+def test_dense_banded_wait_gives_up(pint, orc, pipe):
     w = W.lorenz96(T=2048)
-    print("[waits] lorenz96 T=2048 W=48, wait limit 0", flush=True)
+    print(f"[waits] lorenz96 T=2048 W=48 pipe={pipe}, wait limit 0", flush=True)
     _, _, _, status = _solve_limited(pint, pint.LORENZ96, _t(w.x0), _t(w.params), w.dt, 2048,
-                                     tol=1e-10, window=48)
+                                     tol=1e-10, window=48, pipe=pipe)
     assert int(status[0]) == pint.ERR_DEVICE
     print("[waits] lorenz96 T=2048 W=48, default bound", flush=True)
     traj, iters, resid, status = pint.solve(pint.LORENZ96, _t(w.x0), _t(w.params), w.dt, 2048,
@@ -43,11 +48,12 @@ def test_dense_banded_wait_gives_up(pint, orc):
     assert np.abs(h).max() < 1e-10
 
 
-def test_dense_kuramoto_wait_gives_up(pint, orc):
+@pytest.mark.parametrize("pipe", [True, False])
+def test_dense_kuramoto_wait_gives_up(pint, orc, pipe):
     w = W.kuramoto(B=2, T=512)
-    print("[waits] kuramoto 2 x 512 W=64, wait limit 0", flush=True)
+    print(f"[waits] kuramoto 2 x 512 W=64 pipe={pipe}, wait limit 0", flush=True)
     _, _, _, status = _solve_limited(pint, pint.KURAMOTO, _t(w.x0), _t(w.params), w.dt, 512,
-                                     tol=1e-10, window=64)
+                                     tol=1e-10, window=64, pipe=pipe)
     assert (status == pint.ERR_DEVICE).all()
     traj, iters, resid, status = pint.solve(pint.KURAMOTO, _t(w.x0), _t(w.params), w.dt, 512,
                                             tol=1e-10, window=64)
