@@ -152,10 +152,11 @@ void pint_set_scan_delay(uint32_t sleeps);
 /* The pipelined kernels, on != 0 by default:
  *  - windowed solves of the dense systems (pint_solve of PINT_SYS_LORENZ96
  *    with d = 40, or PINT_SYS_KURAMOTO with d = 64 or 128; window >= 1;
- *    batches of up to 1/4 as many instances as compute units): the
- *    pipelined solver, in which consecutive Newton updates overlap in time
- *    on separate workgroups; 0 the solver that applies one update at a
- *    time.  Both compute the same iteration (same windows, same accepted
+ *    batches of up to as many instances as compute units): the pipelined
+ *    solver, in which consecutive Newton updates overlap in time on
+ *    separate workgroups (up to 16 per instance; with one, an instance's
+ *    updates run in turn, their elements kept on chip); 0 the solver that
+ *    applies one update at a time.  Both compute the same iteration (same windows, same accepted
  *    updates, the same states bit for bit).
  *  - pint_adjoint of Lorenz-96: the fused reverse pass, elements built
  *    inside the recursion; 0 the two-kernel path (elements stored per

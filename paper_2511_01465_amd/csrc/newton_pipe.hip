@@ -1143,14 +1143,16 @@ static int pipe_cus() {
 
 // Agents per instance: 16 (about twice the updates in flight at once for
 // windows of 32-64 steps), fewer when the batch would not fit one agent per
-// compute unit; 0 when the pipeline does not apply.
+// compute unit, down to one (then an instance's updates run one after the
+// other on its agent, still with every element kept in the agent's LDS
+// ring); 0 when the pipeline does not apply.
 static int pipe_agents(const SolveArgs& a) {
   if (a.window <= 0 || a.B <= 0 || a.T_uniform <= 0 || a.T_off) return 0;
   if (a.T_uniform > 0x7fffffffLL) return 0;
   const int cus = pipe_cus();
   int64_t G = 16;
   while (G >= 2 && a.B * G > cus) G /= 2;
-  return G >= 4 ? (int)G : 0;
+  return G >= 1 && a.B * G <= cus ? (int)G : 0;
 }
 
 template <typename T, class S>

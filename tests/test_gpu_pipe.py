@@ -34,8 +34,10 @@ def _both(pint, w, T, dtype=torch.float64, system=None, **kw):
 
 
 @pytest.mark.parametrize("T,window,B", [(256, 32, 1), (300, 120, 1), (2048, 48, 1), (2048, 16, 2),
-                                        (4096, 56, 16), (1000, 1000, 3), (777, 13, 5)])
+                                        (4096, 56, 16), (1000, 1000, 3), (777, 13, 5),
+                                        (512, 24, 256), (600, 32, 100)])
 def test_pipeline_equals_one_at_a_time(pint, T, window, B):
+    # (B = 256 and 100 on a 256-CU device: one and two agents per instance)
     w = W.lorenz96(T=T, B=B)
     print(f"[pipe] T={T} W={window} B={B}", flush=True)
     (tp, ip, rp, sp), (to, io, ro, so) = _both(pint, w, T, tol=1e-10, window=window)
