@@ -1086,7 +1086,7 @@ __global__ __launch_bounds__(64) void k_seq_dense(DenseKArgs a, const int64_t* T
   }
   const T dt = (T)a.dt;
   for (int64_t n = 0; n < Tn; n++) {
-    wave_rk4<T, S>(s_P, dt, x, y, nullptr, lane);
+    wave_rk4<T, S, true>(s_P, dt, x, y, nullptr, lane);
 #pragma unroll
     for (int r = 0; r < R; r++) {
       const int i = lane + 64 * r;

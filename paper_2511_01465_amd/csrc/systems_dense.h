@@ -64,6 +64,7 @@ struct DSysL96 {
   static constexpr int BW = 13, BOFF = 8;
   static_assert(D >= 2 * BW, "band must not wrap onto itself");
 
+  template <bool FAST = false>  // (one form only)
   __device__ static void f(const T* P, const T (&x)[R], T (&out)[R], int lane) {
     const int i = lane < D ? lane : 0;
     const T xp1 = __shfl(x[0], (i + 1) % D, PINT_WAVE);
@@ -250,6 +251,11 @@ struct DSysKur {
   static constexpr int STAGE_SCALARS = 8 * D + 8;
   static_assert(sizeof(StageKur<T, D>) == STAGE_SCALARS * sizeof(T), "stage record layout");
 
+  // FAST: the two wave sums as DPP row permutes (vector ALU) instead of a
+  // shuffle butterfly (LDS unit); different rounding order.  Used where one
+  // wave runs alone (the sequential integrator); the Newton solvers' many
+  // element waves are bound by the vector ALU and keep the butterfly.
+  template <bool FAST = false>
   __device__ static void sums(const T (&x)[R], T (&sn)[R], T (&cs)[R], T& S, T& C, int lane) {
     T ls = T(0), lc = T(0);
 #pragma unroll
@@ -261,12 +267,19 @@ struct DSysKur {
       ls += sn[r];
       lc += cs[r];
     }
-    S = wave_sum(ls);
-    C = wave_sum(lc);
+    if constexpr (FAST) {
+      wave_sum2_dpp(ls, lc);
+      S = ls;
+      C = lc;
+    } else {
+      S = wave_sum(ls);
+      C = wave_sum(lc);
+    }
   }
+  template <bool FAST = false>
   __device__ static void f(const T* P, const T (&x)[R], T (&out)[R], int lane) {
     T sn[R], cs[R], S, C;
-    sums(x, sn, cs, S, C, lane);
+    sums<FAST>(x, sn, cs, S, C, lane);
 #pragma unroll
     for (int r = 0; r < R; r++) out[r] = P[1 + lane + 64 * r] + P[0] * (cs[r] * S - sn[r] * C);
   }
@@ -331,26 +344,27 @@ struct DSysKur {
 
 // One RK4 step of a dense system by one wave.  x: this lane's components of
 // x_{n-1}; returns phi.  If st != nullptr the four stage points are saved.
-template <typename T, class S>
+// FAST selects S::f's other form where it has one (see DSysKur::sums).
+template <typename T, class S, bool FAST = false>
 __device__ __forceinline__ void wave_rk4(const T* P, T dt, const T (&x)[S::R], T (&phi)[S::R],
                                          typename S::Stage* st, int lane) {
   constexpr int R = S::R;
   T k[R], acc[R], y[R];
   const T h2 = T(0.5) * dt, c6 = dt / T(6);
   if (st) S::save_stage(st, 0, x, lane);
-  S::f(P, x, k, lane);
+  S::template f<FAST>(P, x, k, lane);
 #pragma unroll
   for (int r = 0; r < R; r++) { acc[r] = k[r]; y[r] = x[r] + h2 * k[r]; }
   if (st) S::save_stage(st, 1, y, lane);
-  S::f(P, y, k, lane);
+  S::template f<FAST>(P, y, k, lane);
 #pragma unroll
   for (int r = 0; r < R; r++) { acc[r] += T(2) * k[r]; y[r] = x[r] + h2 * k[r]; }
   if (st) S::save_stage(st, 2, y, lane);
-  S::f(P, y, k, lane);
+  S::template f<FAST>(P, y, k, lane);
 #pragma unroll
   for (int r = 0; r < R; r++) { acc[r] += T(2) * k[r]; y[r] = x[r] + dt * k[r]; }
   if (st) S::save_stage(st, 3, y, lane);
-  S::f(P, y, k, lane);
+  S::template f<FAST>(P, y, k, lane);
 #pragma unroll
   for (int r = 0; r < R; r++) phi[r] = x[r] + c6 * (acc[r] + k[r]);
 }
