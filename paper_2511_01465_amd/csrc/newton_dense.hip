@@ -1085,6 +1085,59 @@ __global__ __launch_bounds__(64) void k_seq_dense(DenseKArgs a, const int64_t* T
     x[r] = i < D ? xg[i] : T(0);
   }
   const T dt = (T)a.dt;
+  if constexpr (S::BANDED && D == 40) {
+    // Lorenz-96: lane l holds component (l - 16) mod 40; lanes 16..55 own the
+    // components, lanes 0..15 and 56..63 hold copies.  f reads offsets
+    // -2..+1, so each stage's values are valid two lanes less on the left
+    // and one less on the right: two RK4 steps (eight stages) use up the
+    // copies exactly and leave the owners' states right, and one lane
+    // permutation per two steps refreshes the copies.  Neighbours come by
+    // whole-wave DPP shifts instead of a shuffle per neighbour; the
+    // arithmetic is that of DSysL96::f and wave_rk4 (the same states bit for
+    // bit).
+    constexpr int DPP_WAVE_SHR1 = 0x138;  // lane l <- lane l - 1
+    constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l <- lane l + 1
+    constexpr int HL = 16;                // copies on the left
+    const bool owner = lane >= HL && lane < HL + D;
+    const int comp = (lane + D - HL) % D;
+    const int src = lane < HL ? lane + D : (lane >= HL + D ? lane - D : lane);
+    const T F = s_P[0], h2 = T(0.5) * dt, c6 = dt / T(6);
+    T xr = xg[comp];
+    auto f = [&](T yv) -> T {
+      const T xp1 = dpp_row<DPP_WAVE_SHL1, 0xf>(T(0), yv);
+      const T xm1 = dpp_row<DPP_WAVE_SHR1, 0xf>(T(0), yv);
+      const T xm2 = dpp_row<DPP_WAVE_SHR1, 0xf>(T(0), xm1);
+      return (xp1 - xm2) * xm1 - yv + F;
+    };
+    auto rk4 = [&](T xv) -> T {
+      T k = f(xv);
+      T acc = k, yv = xv + h2 * k;
+      k = f(yv);
+      acc += T(2) * k;
+      yv = xv + h2 * k;
+      k = f(yv);
+      acc += T(2) * k;
+      yv = xv + dt * k;
+      k = f(yv);
+      return xv + c6 * (acc + k);
+    };
+    for (int64_t n = 0; n < Tn; n += 2) {
+      const T x1 = rk4(xr);
+      if (owner) X[n * D + comp] = x1;
+      if (n + 1 >= Tn) break;
+      const T x2 = rk4(x1);
+      if (owner) X[(n + 1) * D + comp] = x2;
+      // the copies take their owners' values
+      if constexpr (sizeof(T) == 8) {
+        const int lo = __builtin_amdgcn_ds_bpermute(src * 4, __double2loint((double)x2));
+        const int hi = __builtin_amdgcn_ds_bpermute(src * 4, __double2hiint((double)x2));
+        xr = (T)__hiloint2double(hi, lo);
+      } else {
+        xr = __int_as_float(__builtin_amdgcn_ds_bpermute(src * 4, __float_as_int((float)x2)));
+      }
+    }
+    return;
+  }
   for (int64_t n = 0; n < Tn; n++) {
     wave_rk4<T, S, true>(s_P, dt, x, y, nullptr, lane);
 #pragma unroll
