@@ -1149,6 +1149,67 @@ __global__ __launch_bounds__(64) void k_seq_dense(DenseKArgs a, const int64_t* T
   }
 }
 
+// Sequential comparator for Kuramoto with d = 64 R (R > 1): the R waves of
+// one workgroup share an instance, one component per lane, so each wave
+// evaluates one sincos per stage point instead of R in a row; the stage
+// sums of sin and cos meet through LDS (wave sums by DPP row permutes, then
+// the R partial sums in wave order).  One barrier per stage (two buffers).
+template <typename T, class S>
+__global__ __launch_bounds__(64 * S::R) void k_seq_kur_split(DenseKArgs a, const int64_t* T_off) {
+  constexpr int D = S::D, NP = S::NP, NW = S::R;
+  static_assert(S::MATFREE && D == 64 * NW && NW > 1, "one component per lane");
+  __shared__ T s_P[NP];
+  __shared__ T s_red[2][NW][2];
+  const int64_t inst = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
+  const T* Pg = static_cast<const T*>(a.params) + inst * a.pstride;
+  for (int i = tid; i < NP; i += 64 * NW) s_P[i] = Pg[i];
+  __syncthreads();
+  const int64_t t0 = T_off ? T_off[inst] : inst * a.T_uniform;
+  const int64_t Tn = (T_off ? T_off[inst + 1] : t0 + a.T_uniform) - t0;
+  T* X = static_cast<T*>(a.traj) + t0 * D;
+  const T* xg = static_cast<const T*>(a.x0) + inst * D;
+  const T dt = (T)a.dt, h2 = T(0.5) * dt, c6 = dt / T(6);
+  const T Kc = s_P[0], om = s_P[1 + tid];
+  int buf = 0;
+  auto f = [&](T y) -> T {
+    T sn, cs;
+    if constexpr (sizeof(T) == 8)
+      sincos(y, &sn, &cs);
+    else
+      sincosf(y, &sn, &cs);
+    T ls = sn, lc = cs;
+    wave_sum2_dpp(ls, lc);
+    if (lane == 0) {
+      s_red[buf][wv][0] = ls;
+      s_red[buf][wv][1] = lc;
+    }
+    __syncthreads();
+    T Ssum = s_red[buf][0][0], Csum = s_red[buf][0][1];
+#pragma unroll
+    for (int w = 1; w < NW; w++) {
+      Ssum += s_red[buf][w][0];
+      Csum += s_red[buf][w][1];
+    }
+    buf ^= 1;
+    return om + Kc * (cs * Ssum - sn * Csum);
+  };
+  T x = xg[tid];
+  for (int64_t n = 0; n < Tn; n++) {
+    T k = f(x);
+    T acc = k, y = x + h2 * k;
+    k = f(y);
+    acc += T(2) * k;
+    y = x + h2 * k;
+    k = f(y);
+    acc += T(2) * k;
+    y = x + dt * k;
+    k = f(y);
+    x = x + c6 * (acc + k);
+    X[n * D + tid] = x;
+  }
+}
+
 // Residual of every step of a uniform batch: one wave per step.
 template <typename T, class S>
 __global__ __launch_bounds__(256) void k_residual_dense(DenseKArgs a, T* h, double* hmax) {
@@ -1388,7 +1449,10 @@ int dense_seq(const SolveArgs& a) {
   return dispatch_dense(a.dtype, a.system, a.d, [&](auto t, auto s) {
     using T = decltype(t);
     using S = decltype(s);
-    hipLaunchKernelGGL((k_seq_dense<T, S>), dim3(a.B), dim3(64), 0, a.stream, k, a.T_off);
+    if constexpr (S::MATFREE && S::R > 1)
+      hipLaunchKernelGGL((k_seq_kur_split<T, S>), dim3(a.B), dim3(64 * S::R), 0, a.stream, k, a.T_off);
+    else
+      hipLaunchKernelGGL((k_seq_dense<T, S>), dim3(a.B), dim3(64), 0, a.stream, k, a.T_off);
     return hipGetLastError() == hipSuccess ? ST_OK : ST_DEVICE;
   });
 }
