@@ -664,23 +664,15 @@ __global__ __launch_bounds__(PIPE_NT) void k_newton_pipe(PipeKArgs a, int G) {
 // the same bit for bit.  D = 64 RC components, RC per lane; the ring holds
 // fewer steps than the banded one (a record is 8 D + 8 values).
 constexpr int PIPE_MF_R = 10;  // ring slots (steps)
-#ifndef PIPE_MF_NT
-#define PIPE_MF_NT 768
-#endif
-#ifndef PIPE_MF_SKIP0
-#define PIPE_MF_SKIP0 0
-#endif
+// 12 waves (768 threads): wave 0 folds, 1 loads, 2 writes, 3..11 build
+// elements.  Building elements (four sincos per component and step) bounds
+// the pipeline's throughput: 5 element waves (512 threads) measured 10.6 ms,
+// 9 (768) 8.6 ms and 13 (1024) 9.2 ms for 8 x 4096 at W = 256 (before the
+// sincos change); keeping the fold's SIMD free of element waves was slower.
+constexpr int PIPE_MF_NT = 768;
 constexpr int PIPE_MF_NW = PIPE_MF_NT / PINT_WAVE;
-// element waves: 3, 4, ... (with PIPE_MF_SKIP0, not those on the fold's SIMD, w % 4 == 0)
-__host__ __device__ constexpr int mf_elem_index(int wv) {
-  if (wv < 3) return -1;
-  if (PIPE_MF_SKIP0 && wv % 4 == 0) return -1;
-  int e = 0;
-  for (int w = 3; w < wv; w++)
-    if (!(PIPE_MF_SKIP0 && w % 4 == 0)) e++;
-  return e;
-}
-constexpr int PIPE_MF_NE = mf_elem_index(PIPE_MF_NW - 1) + 1;
+constexpr int PIPE_MF_NE = PIPE_MF_NW - 3;
+__host__ __device__ constexpr int mf_elem_index(int wv) { return wv >= 3 ? wv - 3 : -1; }
 
 template <typename T, class S>
 struct PipeSmemMF {
