@@ -168,3 +168,20 @@ def test_kuramoto_pipeline_end_conditions(pint, orc):
                                             tol=1e-10, window=32)
     torch.cuda.synchronize()
     assert int(status[0]) == pint.NONFINITE and int(iters[0]) == 0
+
+
+@pytest.mark.parametrize("system", ["lorenz96", "kuramoto"])
+def test_pipeline_repeatable(pint, system):
+    """The pipelined solvers' arithmetic does not depend on how the agents'
+    timing interleaves: repeated solves give the same trajectory bit for bit."""
+    if system == "lorenz96":
+        w, T, win, sid = W.lorenz96(T=2048, B=4), 2048, 48, pint.LORENZ96
+    else:
+        w, T, win, sid = W.kuramoto(B=8, T=512), 512, 64, pint.KURAMOTO
+    outs = []
+    for _ in range(3):
+        outs.append(pint.solve(sid, _t(w.x0), _t(w.params), w.dt, T, tol=1e-10, window=win))
+        torch.cuda.synchronize()
+    for o in outs[1:]:
+        assert torch.equal(o[0], outs[0][0]) and torch.equal(o[1], outs[0][1])
+        assert torch.equal(o[2], outs[0][2]) and torch.equal(o[3], outs[0][3])
