@@ -632,7 +632,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1",
+        print(json.dumps({"error": "bench.py measures one GPU; run with --gpus 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
