@@ -185,3 +185,18 @@ def test_pipeline_repeatable(pint, system):
     for o in outs[1:]:
         assert torch.equal(o[0], outs[0][0]) and torch.equal(o[1], outs[0][1])
         assert torch.equal(o[2], outs[0][2]) and torch.equal(o[3], outs[0][3])
+
+
+@pytest.mark.parametrize("system", ["lorenz96", "kuramoto"])
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_pipeline_tiny_horizons(pint, orc, system, T):
+    """Horizons of one to three steps (window 2): the first window start is
+    step 1 and the state before it is x0; against the oracle."""
+    w = W.lorenz96(T=T, B=2) if system == "lorenz96" else W.kuramoto(B=3, T=T)
+    sid = pint.LORENZ96 if system == "lorenz96" else pint.KURAMOTO
+    traj, iters, resid, status = pint.solve(sid, _t(w.x0), _t(w.params), w.dt, T, tol=1e-10, window=2)
+    torch.cuda.synchronize()
+    for b in range(w.B):
+        ref = orc.newton(w.system, w.params[b], w.dt, T, w.x0[b], tol=1e-10, window=2, max_iter=100)
+        assert int(status[b]) == ref["status"] == 0 and int(iters[b]) == ref["iters"]
+        assert np.abs(traj[b].cpu().numpy() - ref["traj"]).max() <= 1e-10
