@@ -27,6 +27,7 @@
 //   dense d (16..128): each tile folds its elements with MFMA matrix
 //     products (FP64 16x16x4 or FP32 16x16x4), the running product in LDS.
 #include <mutex>
+#include <type_traits>
 
 #include "../../include/pint.h"
 #include "internal.h"
@@ -120,24 +121,49 @@ constexpr int vec_width(int run) {
 }
 
 // Tile shape of the small-d scan: NT threads, S consecutive elements per
-// thread, the tile staged in LDS within a 48 KiB budget (three workgroups
-// per compute unit).  RA / RB: scalars of A / b per thread run.  FP32 runs
-// are sized as FP64 ones (half the budget) for d = 1 and 3, measured faster
-// there (2^24 elements: d = 1 0.092 -> 0.086 ms, d = 3 0.586 -> 0.449 ms),
-// and by their own size for d = 2 (0.195 ms against 0.205 ms).
+// thread in each chunk, a chunk staged in LDS within a 48 KiB budget.  A
+// tile is C chunks: each thread keeps its runs of the first K in registers
+// from the first pass to the second (HC registers a chunk, K*HC within the
+// HOLD budget) and the last stays in LDS, so every element is read from
+// memory once.  PD chunk loads are in flight ahead of the chunk composed;
+// WPE waves per SIMD (two or three workgroups per compute unit) bound the
+// registers.  HOLD, PD and WPE per d and precision are the fastest measured
+// on 2^24 orthogonal elements (FP64 d = 1/2/3: 0.121 / 0.313 / 0.769 ms,
+// FP32: 0.075 / 0.173 / 0.437 ms, against 0.127 / 0.356 / 0.803 and
+// 0.079 / 0.196 / 0.469 ms when every chunk but the last was read again in
+// the second pass).  RA / RB: scalars of A / b per thread run.  FP32 runs are
+// sized as FP64 ones for d = 1 and 3 and by their own size for d = 2.
 template <int D, typename T>
 struct SmallShape {
-  static constexpr int NT = D <= 4 ? 256 : 64;
+  static constexpr bool F64 = sizeof(T) == 8;
+  static constexpr int NT = 256;
   static constexpr int E = D * D + D;
   static constexpr int SB = D == 2 ? (int)sizeof(T) : 8;  // bytes counted per scalar
   static constexpr int S0 = 49152 / (E * SB * NT);
   static constexpr int S = S0 < 1 ? 1 : (S0 > 16 ? 16 : S0);
   static constexpr int CH = NT * S;   // elements per chunk (one LDS staging)
-  static constexpr int C = D == 1 ? 12 : 8;  // chunks per tile (one lookback per tile)
+  static constexpr int HC = S * E * (int)sizeof(T) / 4;  // registers per kept chunk
+  static constexpr int HOLD = F64 ? (D == 1 ? 144 : D == 2 ? 48 : 96) : (D == 1 ? 48 : D == 2 ? 144 : 72);
+  static constexpr int PD0 = D == 3 ? 2 : 1;
+  static constexpr int WPE = F64 ? (D == 2 ? 3 : 2) : (D == 2 ? 2 : 3);
+  static constexpr int K0 = HOLD / HC;
+  static constexpr int K = K0 < 1 ? 1 : (K0 > 11 ? 11 : K0);  // chunks kept in registers
+  static constexpr int C = K + 1;     // chunks per tile (one lookback per tile)
+  static constexpr int PD = PD0 < C ? PD0 : C;
   static constexpr int TILE = CH * C;
   static constexpr int RA = S * D * D, RB = S * D;
   static constexpr int VA = vec_width<T>(RA), VB = vec_width<T>(RB);
 };
+
+// f(integral_constant<int, i>) for i = I .. N-1 in turn: a loop whose index
+// is a compile-time constant, so it can select a register array.
+template <int I, int N, typename F>
+__device__ __forceinline__ void unroll_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    unroll_for<I + 1, N>(f);
+  }
+}
 
 // Global -> LDS copy of n <= NT*RUN scalars into the blocked layout in which
 // thread t's run of RUN scalars starts at t*(RUN+1) (one pad scalar per run,
@@ -243,27 +269,28 @@ __device__ __forceinline__ void stash_run(T* lds, int n, int tid, const RunRegs<
     }
 }
 
-// A tile is C chunks of NT*S elements.  Pass 1 stages the chunks in turn
-// and composes their aggregates into the tile's; after the lookback, pass 2
-// stages them again (the second read mostly hits the last-level cache) and
-// writes the outputs.  One lookback per C chunks.  Pass 1 keeps each chunk's
-// aggregate, so after the lookback the z at every chunk start is known and
-// pass 2 walks the chunks backwards: the last one is still in LDS and the
-// others come back most recent first, while they are likeliest to be cached.
-// A chunk's loads go to registers one chunk ahead (the first of pass 2
-// during the lookback), and the barriers between order LDS only, so the
-// loads stay in flight while the previous chunk is composed.
+// A tile is C chunks of NT*S elements, each staged once through LDS.  Pass 1
+// folds the chunks in turn into the tile's aggregate, keeping each chunk's
+// aggregate and, in registers, each thread's runs of the first K chunks (the
+// last chunk stays in LDS).  One lookback per tile gives the z at the tile
+// start, hence at every chunk start; pass 2 walks the chunks backwards (the
+// last one first, while LDS still holds it), refolds each thread's run for
+// its offset within the chunk and writes the outputs.  A chunk's loads go to
+// registers PD chunks ahead, and the barriers between order LDS only, so
+// the loads stay in flight while the previous chunk is composed.
 template <typename T, int D>
-__global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs a) {
+__global__ __launch_bounds__((SmallShape<D, T>::NT)) __attribute__((amdgpu_waves_per_eu(SmallShape<D, T>::WPE)))
+void k_scan_small(ScanArgs a) {
   using SH = SmallShape<D, T>;
   constexpr int NT = SH::NT, S = SH::S, CH = SH::CH, TILE = SH::TILE, NW = NT / PINT_WAVE, E = SH::E;
+  constexpr int C = SH::C, K = SH::K;
   constexpr int RA = SH::RA, RB = SH::RB, PA = RA + 1, PB = RB + 1;
   __shared__ T sA[NT * PA];
   __shared__ T sb[NT * PB];
   __shared__ Aff<T, D> s_aff[NW];
   __shared__ Aff<T, D> s_tagg;
-  __shared__ Aff<T, D> s_cagg[SH::C];  // each chunk's aggregate (pass 1)
-  __shared__ T s_zc[SH::C][D];         // z at each chunk start (after the lookback)
+  __shared__ Aff<T, D> s_cagg[C];  // each chunk's aggregate (pass 1)
+  __shared__ T s_zc[C][D];         // z at each chunk start (after the lookback)
   __shared__ T s_wz[NW][D];
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, lane = tid % PINT_WAVE, wv = tid / PINT_WAVE;
@@ -282,32 +309,28 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
   const T* myA = sA + tid * PA;
   const T* myb = sb + tid * PB;
 
-  RunRegs<T, RA, SH::VA> rA;
-  RunRegs<T, RB, SH::VB> rB;
+  constexpr int PD = SH::PD;  // chunks in flight ahead of the one composed
+  RunRegs<T, RA, SH::VA> rA[PD];
+  RunRegs<T, RB, SH::VB> rB[PD];
+  T hA[K][RA], hb[K][RB];  // this thread's runs of chunks 0..K-1
   auto chunk_len = [&](int c) { return (n_el - c * CH) < CH ? (n_el - c * CH) : CH; };
-  auto fetch = [&](int c) {
+  auto fetch = [&](int c, auto& ra, auto& rb) __attribute__((always_inline)) {
     const int c0 = c * CH, n = chunk_len(c);
-    fetch_run<T, RA, SH::VA, NT>(Ag + (int64_t)c0 * D * D, n * D * D, tid, rA);
-    fetch_run<T, RB, SH::VB, NT>(bg + (int64_t)c0 * D, n * D, tid, rB);
+    fetch_run<T, RA, SH::VA, NT>(Ag + (int64_t)c0 * D * D, n * D * D, tid, ra);
+    fetch_run<T, RB, SH::VB, NT>(bg + (int64_t)c0 * D, n * D, tid, rb);
   };
-  // chunk c (its registers) into LDS, the loads of chunk `next` (if >= 0)
-  // issued; each thread folds its S elements; block scan: agg = composition
-  // of threads 0..tid of the chunk
-  auto chunk_scan = [&](int c, int next, Aff<T, D>& agg, int& cn) {
-    cn = chunk_len(c);
-    stash_run<T, RA, SH::VA, NT>(sA, cn * D * D, tid, rA);
-    stash_run<T, RB, SH::VB, NT>(sb, cn * D, tid, rB);
-    lds_barrier();
-    if (next >= 0) fetch(next);
+  // this thread's run (registers or LDS) folded, then the block scan: agg =
+  // composition of the runs of threads 0..tid of the chunk
+  auto run_scan = [&](const T* ra, const T* rb, int cn, Aff<T, D>& agg) __attribute__((always_inline)) {
     aff_identity(agg);
 #pragma unroll
     for (int s = 0; s < S; s++) {
       if (tid * S + s < cn) {
         Aff<T, D> e;
 #pragma unroll
-        for (int i = 0; i < D * D; i++) e.A[i] = myA[s * D * D + i];
+        for (int i = 0; i < D * D; i++) e.A[i] = ra[s * D * D + i];
 #pragma unroll
-        for (int i = 0; i < D; i++) e.b[i] = myb[s * D + i];
+        for (int i = 0; i < D; i++) e.b[i] = rb[s * D + i];
         aff_after(e, agg);
         agg = e;
       }
@@ -318,21 +341,36 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
   // pass 1: the tile's aggregate
   Aff<T, D> agg;
   int cn = 0;
-  fetch(0);
-  for (int c = 0; c < nch; c++) {
-    chunk_scan(c, c + 1 < nch ? c + 1 : -1, agg, cn);
-    if (tid == NT - 1) {
-      s_cagg[c] = agg;
-      Aff<T, D> t = agg;
-      aff_after(t, s_tagg);  // this chunk after the earlier ones
-      s_tagg = t;
+  unroll_for<0, PD>([&](auto ci) __attribute__((always_inline)) {
+    constexpr int c = decltype(ci)::value;
+    if (c < nch) fetch(c, rA[c], rB[c]);
+  });
+  unroll_for<0, C>([&](auto ci) __attribute__((always_inline)) {
+    constexpr int c = decltype(ci)::value;
+    if (c < nch) {
+      cn = chunk_len(c);
+      stash_run<T, RA, SH::VA, NT>(sA, cn * D * D, tid, rA[c % PD]);
+      stash_run<T, RB, SH::VB, NT>(sb, cn * D, tid, rB[c % PD]);
+      lds_barrier();
+      if (c + PD < nch) fetch(c + PD, rA[c % PD], rB[c % PD]);
+      if constexpr (c < K) {
+#pragma unroll
+        for (int i = 0; i < RA; i++) hA[c][i] = myA[i];
+#pragma unroll
+        for (int i = 0; i < RB; i++) hb[c][i] = myb[i];
+        run_scan(hA[c], hb[c], cn, agg);
+      } else {
+        run_scan(myA, myb, cn, agg);
+      }
+      if (tid == NT - 1) {
+        s_cagg[c] = agg;
+        Aff<T, D> t = agg;
+        aff_after(t, s_tagg);  // this chunk after the earlier ones
+        s_tagg = t;
+      }
+      if (c + 1 < nch) lds_barrier();  // the chunk's LDS may be rewritten
     }
-    if (c + 1 < nch) lds_barrier();  // the chunk's LDS may be rewritten
-  }
-  // pass 2's first reload (chunk nch-2) during the lookback (wave 0's share
-  // after it: its flag stores wait for all of its outstanding memory
-  // operations); the last chunk is still in LDS and `agg` is its scan
-  if (nch > 1 && wv != 0) fetch(nch - 2);
+  });
   lds_barrier();  // s_tagg, s_cagg written
   // lookback by wave 0: z at the start of this tile
   if (wv == 0) {
@@ -434,64 +472,78 @@ __global__ __launch_bounds__((SmallShape<D, T>::NT)) void k_scan_small(ScanArgs 
       }
       publish_flag(flags, ts, FLAG_INCL, a.delay);
     }
-    if (nch > 1) fetch(nch - 2);
   }
-  lds_barrier();  // s_zc written (the prefetched loads stay in flight)
+  lds_barrier();  // s_zc written
 
-  // pass 2: outputs chunk by chunk, last chunk first (it is still in LDS)
+  // pass 2: outputs chunk by chunk, last chunk first (agg and cn are still
+  // pass 1's for it); the chunks before it are refolded from registers
   T* zg = static_cast<T*>(a.z) + (seq * a.N + e0) * D;
-  for (int c = nch - 1; c >= 0; c--) {
-    if (c < nch - 1) chunk_scan(c, c > 0 ? c - 1 : -1, agg, cn);
-    // z at the end of each thread's run, then at its start (previous thread)
-    T zin[D], zend[D], z[D];
-#pragma unroll
-    for (int i = 0; i < D; i++) zin[i] = s_zc[c][i];
-#pragma unroll
-    for (int i = 0; i < D; i++) {
-      T acc = agg.b[i];
-#pragma unroll
-      for (int k = 0; k < D; k++) acc += agg.A[i * D + k] * zin[k];
-      zend[i] = acc;
-    }
-    if (lane == PINT_WAVE - 1)
-#pragma unroll
-      for (int i = 0; i < D; i++) s_wz[wv][i] = zend[i];
-    lds_barrier();
-#pragma unroll
-    for (int i = 0; i < D; i++) {
-      const T up = __shfl_up(zend[i], 1, PINT_WAVE);
-      z[i] = lane > 0 ? up : (wv > 0 ? s_wz[wv - 1][i] : zin[i]);
-    }
-    T out[S][D];
-#pragma unroll
-    for (int s = 0; s < S; s++) {
-      if (tid * S + s < cn) {
-        T t[D];
-#pragma unroll
-        for (int i = 0; i < D; i++) {
-          T acc = myb[s * D + i];
-#pragma unroll
-          for (int k = 0; k < D; k++) acc += myA[s * D * D + i * D + k] * z[k];
-          t[i] = acc;
-        }
-#pragma unroll
-        for (int i = 0; i < D; i++) {
-          z[i] = t[i];
-          out[s][i] = t[i];
+  unroll_for<0, C>([&](auto ci) __attribute__((always_inline)) {
+    constexpr int c = C - 1 - decltype(ci)::value;
+    if (c < nch) {
+      if constexpr (c < K) {
+        if (c < nch - 1) {
+          cn = chunk_len(c);
+          run_scan(hA[c], hb[c], cn, agg);
         }
       }
-    }
-    lds_barrier();  // every thread has read s_wz and its b run
+      // z at the end of each thread's run, then at its start (previous thread)
+      T zin[D], zend[D], z[D];
 #pragma unroll
-    for (int s = 0; s < S; s++) {
-      if (tid * S + s < cn)
+      for (int i = 0; i < D; i++) zin[i] = s_zc[c][i];
 #pragma unroll
-        for (int i = 0; i < D; i++) sb[tid * PB + s * D + i] = out[s][i];
+      for (int i = 0; i < D; i++) {
+        T acc = agg.b[i];
+#pragma unroll
+        for (int k = 0; k < D; k++) acc += agg.A[i * D + k] * zin[k];
+        zend[i] = acc;
+      }
+      if (lane == PINT_WAVE - 1)
+#pragma unroll
+        for (int i = 0; i < D; i++) s_wz[wv][i] = zend[i];
+      lds_barrier();
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T up = __shfl_up(zend[i], 1, PINT_WAVE);
+        z[i] = lane > 0 ? up : (wv > 0 ? s_wz[wv - 1][i] : zin[i]);
+      }
+      T out[S][D];
+      auto outputs = [&](const T* ra, const T* rb) __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+          if (tid * S + s < cn) {
+            T t[D];
+#pragma unroll
+            for (int i = 0; i < D; i++) {
+              T acc = rb[s * D + i];
+#pragma unroll
+              for (int k = 0; k < D; k++) acc += ra[s * D * D + i * D + k] * z[k];
+              t[i] = acc;
+            }
+#pragma unroll
+            for (int i = 0; i < D; i++) {
+              z[i] = t[i];
+              out[s][i] = t[i];
+            }
+          }
+        }
+      };
+      if constexpr (c < K)
+        outputs(hA[c], hb[c]);
+      else
+        outputs(myA, myb);
+      lds_barrier();  // every thread has read s_wz and its b run
+#pragma unroll
+      for (int s = 0; s < S; s++) {
+        if (tid * S + s < cn)
+#pragma unroll
+          for (int i = 0; i < D; i++) sb[tid * PB + s * D + i] = out[s][i];
+      }
+      lds_barrier();
+      stage_out<T, RB, SH::VB, NT>(zg + (int64_t)c * CH * D, sb, cn * D, tid);
+      lds_barrier();  // the staging area is reloaded by the next chunk
     }
-    lds_barrier();
-    stage_out<T, RB, SH::VB, NT>(zg + (int64_t)c * CH * D, sb, cn * D, tid);
-    lds_barrier();  // the staging area is reloaded by the next chunk
-  }
+  });
 }
 
 // ------------------------------------------------------- d = 4 .. 8 ------

@@ -80,6 +80,22 @@ def test_struct_layout_matches_the_header(tmp_path, struct):
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libpint.so not built")
+def test_small_scan_tile_lengths():
+    """The tile lengths that size the small-d scan parity cases are the
+    library's: sequences of one tile take the workspace of one-element
+    sequences, and one element more takes a second tile each."""
+    import paper_2511_01465_amd as P
+    from test_gpu_scan import SMALL_TILE
+    P.load()
+    B = 1000
+    for dt, code in (("f64", P.F64), ("f32", P.F32)):
+        for d, L in SMALL_TILE[dt].items():
+            one = P.pint_scan_workspace_bytes(d, B, 1, 0, code)
+            assert P.pint_scan_workspace_bytes(d, B, L, 0, code) == one, (dt, d, L)
+            assert P.pint_scan_workspace_bytes(d, B, L + 1, 0, code) > one, (dt, d, L)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpint.so not built")
 def test_step_rule_argument_checks():
     """The one-step rule is checked on the host: unknown codes and a non-zero
     reserved word are invalid; the implicit rules exist for the small

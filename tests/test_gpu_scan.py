@@ -12,9 +12,12 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
-# elements per tile of the small-d kernels (FP64): 12 (d = 1) or 8 chunks of
-# 256 threads x S elements for d <= 3, 64 lanes x 64 elements for d >= 4
-SMALL_TILE = {1: 36864, 2: 8192, 3: 4096, 4: 4096, 5: 4096, 6: 4096, 7: 4096, 8: 4096}
+# elements per tile of the small-d kernels: for d <= 3 a few chunks of 256
+# threads x S elements (all but the last kept in registers between the two
+# passes), for d >= 4 64 lanes x 64 elements; and per chunk for d <= 3
+SMALL_TILE = {"f64": {1: 12288, 2: 2048, 3: 1536, 4: 4096, 5: 4096, 6: 4096, 7: 4096, 8: 4096},
+              "f32": {1: 9216, 2: 8192, 3: 2048, 4: 4096, 5: 4096, 6: 4096, 7: 4096, 8: 4096}}
+SMALL_CHUNK = {"f64": {1: 3072, 2: 1024, 3: 512}, "f32": {1: 3072, 2: 2048, 3: 512}}
 
 
 def _ref(orc, A, b, z0):
@@ -45,10 +48,21 @@ def _check(pint, orc, d, N, B, dtype, with_z0, seed, tile=0):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_small_d_several_tiles_ragged(pint, orc, d, dtype):
-    tile = SMALL_TILE[d] if dtype == "f64" else None
-    N = 3 * (tile or SMALL_TILE[d]) + 17
+    N = 3 * SMALL_TILE[dtype][d] + 17
     print(f"[scan] d={d} {dtype} N={N}", flush=True)
     _check(pint, orc, d, N, 3, dtype, True, seed=10 + d)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("extra", [1, 2])
+def test_small_d_tail_chunks(pint, orc, d, dtype, extra):
+    """A last tile that ends inside its second or third chunk: its earlier
+    chunks are full, and the one it ends in is a chunk the second pass takes
+    from registers (or, at the tile's chunk count, from LDS)."""
+    N = 2 * SMALL_TILE[dtype][d] + extra * SMALL_CHUNK[dtype][d] + 29
+    print(f"[scan] tail d={d} {dtype} N={N}", flush=True)
+    _check(pint, orc, d, N, 2, dtype, True, seed=60 + d + 10 * extra)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -122,7 +136,7 @@ def test_many_tiles_mixed(pint, orc, d, dtype):
     """Several times more tiles than workgroups resident on the device, three
     sequences of odd length so that later sequences start misaligned for
     vector loads and end ragged."""
-    N = 100 * SMALL_TILE[d] + 17
+    N = 100 * SMALL_TILE[dtype][d] + 17
     print(f"[scan] many tiles d={d} {dtype} N={N} B=3", flush=True)
     _check(pint, orc, d, N, 3, dtype, True, seed=40 + d)
 
