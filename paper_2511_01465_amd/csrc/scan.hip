@@ -128,10 +128,10 @@ constexpr int vec_width(int run) {
 // memory once.  PD chunk loads are in flight ahead of the chunk composed;
 // WPE waves per SIMD (two or three workgroups per compute unit) bound the
 // registers.  HOLD, PD and WPE per d and precision are the fastest measured
-// on 2^24 orthogonal elements (FP64 d = 1/2/3: 0.121 / 0.313 / 0.769 ms,
-// FP32: 0.075 / 0.173 / 0.437 ms, against 0.127 / 0.356 / 0.803 and
+// on 2^24 orthogonal elements (FP64 d = 1/2/3: 0.118 / 0.304 / 0.766 ms,
+// FP32: 0.074 / 0.172 / 0.428 ms, against 0.127 / 0.356 / 0.80 and
 // 0.079 / 0.196 / 0.469 ms when every chunk but the last was read again in
-// the second pass).  RA / RB: scalars of A / b per thread run.  FP32 runs are
+// the second pass); two chunks in flight were no faster.  RA / RB: scalars of A / b per thread run.  FP32 runs are
 // sized as FP64 ones for d = 1 and 3 and by their own size for d = 2.
 template <int D, typename T>
 struct SmallShape {
@@ -143,16 +143,17 @@ struct SmallShape {
   static constexpr int S = S0 < 1 ? 1 : (S0 > 16 ? 16 : S0);
   static constexpr int CH = NT * S;   // elements per chunk (one LDS staging)
   static constexpr int HC = S * E * (int)sizeof(T) / 4;  // registers per kept chunk
-  static constexpr int HOLD = F64 ? (D == 1 ? 144 : D == 2 ? 48 : 96) : (D == 1 ? 48 : D == 2 ? 144 : 72);
-  static constexpr int PD0 = D == 3 ? 2 : 1;
+  static constexpr int HOLD = F64 ? (D == 1 ? 144 : 48) : (D == 1 ? 48 : D == 2 ? 144 : 72);
+  static constexpr int PD0 = 1;
   static constexpr int WPE = F64 ? (D == 2 ? 3 : 2) : (D == 2 ? 2 : 3);
   static constexpr int K0 = HOLD / HC;
   static constexpr int K = K0 < 1 ? 1 : (K0 > 11 ? 11 : K0);  // chunks kept in registers
   static constexpr int C = K + 1;     // chunks per tile (one lookback per tile)
   static constexpr int PD = PD0 < C ? PD0 : C;
-  // d <= 2: each thread's prefix within a kept chunk is kept from pass 1 too,
-  // so pass 2 does not refold it (FP64 d = 2: 0.322 -> 0.304 ms)
-  static constexpr bool KA = D <= 2;
+  // each thread's prefix within a kept chunk is kept from pass 1 too, so
+  // pass 2 does not refold it (FP64 d = 2: 0.322 -> 0.304 ms); not for FP32
+  // d = 3, whose three kept chunks leave no registers for it
+  static constexpr bool KA = D <= 2 || F64;
   static constexpr int TILE = CH * C;
   static constexpr int RA = S * D * D, RB = S * D;
   static constexpr int VA = vec_width<T>(RA), VB = vec_width<T>(RB);
@@ -278,8 +279,8 @@ __device__ __forceinline__ void stash_run(T* lds, int n, int tid, const RunRegs<
 // last chunk stays in LDS).  One lookback per tile gives the z at the tile
 // start, hence at every chunk start; pass 2 walks the chunks backwards (the
 // last one first, while LDS still holds it), takes each thread's prefix
-// within the chunk (kept from pass 1 for d <= 2, else refolded from the run
-// in registers) and writes the outputs.  A chunk's loads go to
+// within the chunk (kept from pass 1, or for FP32 d = 3 refolded from the
+// run in registers) and writes the outputs.  A chunk's loads go to
 // registers PD chunks ahead, and the barriers between order LDS only, so
 // the loads stay in flight while the previous chunk is composed.
 template <typename T, int D>

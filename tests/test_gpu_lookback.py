@@ -39,7 +39,7 @@ def _scan(P, A, b, z0, tile):
     return z, ws
 
 
-# (d, B, N, tile): small-d kernels at their own tile lengths (d <= 3: 1536 to
+# (d, B, N, tile): small-d kernels at their own tile lengths (d <= 3: 1024 to
 # 12288 elements per tile, d >= 4: 4096), dense d on MFMA at explicit tiles
 CASES = [(2, 1, 70000, 0), (3, 2, 33000, 0), (5, 1, 30000, 0), (8, 1, 20000, 0),
          (40, 2, 1500, 32), (128, 2, 400, 16)]

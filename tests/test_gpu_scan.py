@@ -15,7 +15,7 @@ DEV = "cuda:0"
 # elements per tile of the small-d kernels: for d <= 3 a few chunks of 256
 # threads x S elements (all but the last kept in registers between the two
 # passes), for d >= 4 64 lanes x 64 elements; and per chunk for d <= 3
-SMALL_TILE = {"f64": {1: 12288, 2: 2048, 3: 1536, 4: 4096, 5: 4096, 6: 4096, 7: 4096, 8: 4096},
+SMALL_TILE = {"f64": {1: 12288, 2: 2048, 3: 1024, 4: 4096, 5: 4096, 6: 4096, 7: 4096, 8: 4096},
               "f32": {1: 9216, 2: 8192, 3: 2048, 4: 4096, 5: 4096, 6: 4096, 7: 4096, 8: 4096}}
 SMALL_CHUNK = {"f64": {1: 3072, 2: 1024, 3: 512}, "f32": {1: 3072, 2: 2048, 3: 512}}
 
