@@ -122,7 +122,8 @@ def _time(fn, reps, stream):
 
 def leg_scan_small(P, torch, dev, stream, reps=5):
     """Small-d affine scan alone on 2^24 orthogonal elements per d (HBM bound):
-    algorithmic bytes per element (d^2 + d) * 8 read + d * 8 written.  A seeded
+    algorithmic bytes per element (d^2 + d) * s read + d * s written, s = 8
+    (FP64) or 4 (FP32).  A seeded
     block of 2^20 random rotations is repeated 16 times (products stay
     orthogonal, so the scan stays bounded)."""
     import workloads as W
@@ -138,23 +139,32 @@ def leg_scan_small(P, torch, dev, stream, reps=5):
     del src, dst
     torch.cuda.empty_cache()
     N = 1 << 24
-    for d in (2, 3, 4, 8):
-        A = torch.empty((1, N, d, d), dtype=torch.float64, device=dev)
-        b = torch.empty((1, N, d), dtype=torch.float64, device=dev)
+    # FP64 d = 1, 2, 3, 4, 8; FP32 (the same rotations rounded, bytes at 4
+    # per scalar) for d = 1, 2, 3 under "fp32"
+    for d, tdt, code in ((1, torch.float64, P.F64), (2, torch.float64, P.F64), (3, torch.float64, P.F64),
+                         (4, torch.float64, P.F64), (8, torch.float64, P.F64),
+                         (1, torch.float32, P.F32), (2, torch.float32, P.F32), (3, torch.float32, P.F32)):
+        A = torch.empty((1, N, d, d), dtype=tdt, device=dev)
+        b = torch.empty((1, N, d), dtype=tdt, device=dev)
         # one seeded block of 2^20 rotations, repeated over the stream
         chunk = 1 << 20
         Ah, bh = W.random_affine(chunk, d, seed=d, kind="rotation")
-        Ad, bd = torch.from_numpy(Ah).to(dev), torch.from_numpy(bh).to(dev)
+        Ad, bd = torch.from_numpy(Ah).to(dev, tdt), torch.from_numpy(bh).to(dev, tdt)
         for c0 in range(0, N, chunk):
             A[0, c0:c0 + chunk] = Ad
             b[0, c0:c0 + chunk] = bd
         del Ad, bd
-        z = torch.empty((1, N, d), dtype=torch.float64, device=dev)
-        ws = torch.empty(P.pint_scan_workspace_bytes(d, 1, N, 0, P.F64), dtype=torch.uint8, device=dev)
-        ms = _time(lambda: P.pint_affine_scan(d, 1, N, P.F64, A, b, None, z, 0, ws, stream), reps, stream)
-        byt = N * ((d * d + d) * 8 + d * 8)
-        out[f"d{d}"] = {"ms": ms, "GB/s": byt / (ms / 1e3) / 1e9, "frac_hbm": byt / (ms / 1e3) / PEAK_HBM,
-                        "frac_of_copy": byt / (ms / 1e3) / copy_bw, "bytes_per_launch": byt, "elements": N}
+        z = torch.empty((1, N, d), dtype=tdt, device=dev)
+        ws = torch.empty(P.pint_scan_workspace_bytes(d, 1, N, 0, code), dtype=torch.uint8, device=dev)
+        ms = _time(lambda: P.pint_affine_scan(d, 1, N, code, A, b, None, z, 0, ws, stream), reps, stream)
+        sb = 8 if tdt == torch.float64 else 4
+        byt = N * ((d * d + d) * sb + d * sb)
+        rec = {"ms": ms, "GB/s": byt / (ms / 1e3) / 1e9, "frac_hbm": byt / (ms / 1e3) / PEAK_HBM,
+               "frac_of_copy": byt / (ms / 1e3) / copy_bw, "bytes_per_launch": byt, "elements": N}
+        if tdt == torch.float64:
+            out[f"d{d}"] = rec
+        else:
+            out.setdefault("fp32", {})[f"d{d}"] = rec
         del A, b, z, ws
         torch.cuda.empty_cache()
     return out
